@@ -1,0 +1,145 @@
+"""Pins of the multilayer-sphere series and the oracle's physics.
+
+The series is checked against (1) the textbook homogeneous sphere and the
+centred-dipole formula, (2) equal-conductivity shells collapsing to one
+sphere, and (3) an independent solve of the interface conditions as a linear
+system.  The oracle's lead field is then checked
+against the series: its error must shrink as the mesh is refined.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fem, leadfield as lf, solve, source, sphere
+from paper_1811_07717_amd import headmodel as hm
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+RADII = [r * 1e-3 for r in hm.RADII_MM]
+
+
+def test_homogeneous_factor_textbook():
+    R, s = 0.092, 0.33
+    for n in (1, 2, 5, 17, 60):
+        rho = 0.05
+        ref = rho ** (n - 1) * (2 * n + 1) / (n * R ** (n + 1)) / (4 * math.pi * s)
+        assert sphere.radial_factor(n, rho, [R], [s]) == pytest.approx(ref, rel=1e-12)
+
+
+def test_equal_conductivity_shells_are_homogeneous():
+    s = 0.41
+    for n in (1, 3, 10, 40, 120):
+        a = sphere.radial_factor(n, 0.06, RADII, [s] * 4)
+        b = sphere.radial_factor(n, 0.06, [RADII[-1]], [s])
+        assert a == pytest.approx(b, rel=1e-11)
+
+
+def test_centred_dipole_closed_form():
+    R, s = 0.092, 0.33
+    pts = hm.fibonacci_centres(20, R)
+    q = np.array([0.2, -0.5, 1.0])
+    v = sphere.potential(pts, np.zeros(3), q, [R], [s])
+    np.testing.assert_allclose(v, 3 * (pts / R) @ q / (4 * math.pi * s * R ** 2), rtol=1e-13)
+
+
+def _linear_system_factor(n, rho, radii, sig):
+    """Radial factor from the (2K-1) interface equations, solved directly.
+
+    Unknowns: a_1 (shell 1: r^-(n+1)/(4 pi s1) + a_1 r^n) and a_k, b_k
+    (shell k >= 2: a_k r^n + b_k r^-(n+1)); continuity of u and sigma u' at
+    r_1..r_{K-1}; u'(r_K) = 0.  Radii rescaled to r_K = 1 for conditioning.
+    """
+    K = len(radii)
+    sc = radii[-1]
+    r = [x / sc for x in radii]
+    N = 2 * K - 1
+    M = np.zeros((N, N))
+    rhs = np.zeros(N)
+    src = 1.0 / (4 * math.pi * sig[0])
+
+    def f(rr):
+        return rr ** n, rr ** (-(n + 1))
+
+    def df(rr):
+        return n * rr ** (n - 1), -(n + 1) * rr ** (-(n + 2))
+
+    def cols(k):   # unknown indices of shell k (0-based)
+        return (0, None) if k == 0 else (2 * k - 1, 2 * k)
+
+    row = 0
+    for k in range(K - 1):
+        rr = r[k]
+        for deriv in (False, True):
+            g = df(rr) if deriv else f(rr)
+            w_in = sig[k] if deriv else 1.0
+            w_out = sig[k + 1] if deriv else 1.0
+            ai, bi = cols(k)
+            M[row, ai] += w_in * g[0]
+            if bi is None:
+                rhs[row] -= w_in * src * g[1]
+            else:
+                M[row, bi] += w_in * g[1]
+            ao, bo = cols(k + 1)
+            M[row, ao] -= w_out * g[0]
+            M[row, bo] -= w_out * g[1]
+            row += 1
+    g = df(r[-1])
+    ak, bk = cols(K - 1)
+    if bk is None:
+        M[row, ak] = g[0]
+        rhs[row] = -src * g[1]
+    else:
+        M[row, ak], M[row, bk] = g[0], g[1]
+    sol = np.linalg.solve(M, rhs)
+    ak, bk = cols(K - 1)
+    uK = sol[ak] + (src if bk is None else sol[bk])
+    # undo the rescaling: r^n and r^-(n+1) terms with rho^(n-1) in physical units
+    return uK * (rho / sc) ** (n - 1) / sc ** 2
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 9, 20])
+def test_four_shell_factor_against_linear_system(n):
+    a = sphere.radial_factor(n, 0.05, RADII, hm.SIGMAS)
+    b = _linear_system_factor(n, 0.05, RADII, hm.SIGMAS)
+    assert a == pytest.approx(b, rel=1e-9)
+
+
+def test_series_converges_and_is_harmonic_sum():
+    # Truncation check: the potential changes by < 1e-12 when the tolerance
+    # is tightened, and the mean over a fine sphere grid is ~0 (no monopole).
+    pts = hm.fibonacci_centres(2000, RADII[-1])
+    r0 = np.array([0.02, -0.03, 0.04])
+    q = np.array([1.0, 0.5, -0.2])
+    v1 = sphere.potential(pts, r0, q, RADII, hm.SIGMAS, rel_tol=1e-12)
+    v2 = sphere.potential(pts, r0, q, RADII, hm.SIGMAS, rel_tol=1e-15)
+    assert np.abs(v1 - v2).max() <= 1e-10 * np.abs(v2).max()
+    assert abs(v2.mean()) <= 1e-3 * np.abs(v2).max()
+
+
+def _guards_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_physics_guards", os.path.join(GOLDEN, "make_physics_guards.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("case", ["homogeneous", "four_layer"])
+def test_oracle_converges_to_sphere_series(case):
+    # The paper prints no accuracy figures, so this is a convergence check:
+    # mean RDM and |MAG-1| over 18 lead-field columns must drop from 8 mm to
+    # 4 mm, and stay within the guards frozen from the first oracle run
+    # (tests/golden/physics_guards.json, written by make_physics_guards.py).
+    sig = (0.33,) * 4 if case == "homogeneous" else hm.SIGMAS
+    with open(os.path.join(GOLDEN, "physics_guards.json")) as f:
+        guards = json.load(f)[case]
+    mod = _guards_module()
+    e8 = mod.physics_errors(8.0, sig)
+    e4 = mod.physics_errors(4.0, sig)
+    assert e4[0] < e8[0] and e4[1] < e8[1]
+    for h, e in (("8", e8), ("4", e4)):
+        assert e[0] <= guards[h]["rdm"] * 1.05
+        assert e[1] <= guards[h]["mag"] * 1.05
