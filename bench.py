@@ -1,0 +1,179 @@
+"""Lead-field build benchmark on one MI355X.
+
+One step = the whole hot path on device-resident inputs:
+zi_assemble (stiffness + CEM + ground) -> zi_transfer_solve (Jacobi PCG on all
+electrode columns to relative residual 1e-8) -> zi_leadfield (Schur complement,
+Cholesky, T^T G, matrix-core product).  The dipole source matrix G is built
+once before timing (it is an input of the lead-field stage).
+
+Prints one JSON line (rank 0).  Default workload: the 2 mm four-layer sphere
+with 128 electrodes and 10 000 dipoles x 3 orientations.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LF build s and electrode-solves/s at rel.resid 1e-8; SpMM HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1811_07717_amd/csrc/k_pcg.hip"]
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="sphere2mm_L128")
+    p.add_argument("--tile", type=int, default=-1)
+    p.add_argument("--precond", default="jacobi")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calib-copy-mb", type=int, default=0,
+                   help="also run one torch copy of this many MiB (counter calibration)")
+    return p.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(workload, {}).get(kernel)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(H, L):
+    """Oracle (plain NumPy/SciPy FP64) on a bounded sample of the workload:
+    full assembly plus the PCG of one electrode column, extrapolated to the
+    L columns of one lead-field build."""
+    from oracle import fem, solve
+    t0 = time.perf_counter()
+    S = fem.assemble(H.nodes, H.tets, H.sigma, H.tris, H.tri_electrode, H.Z)
+    t_asm = time.perf_counter() - t0
+    d = fem.preconditioner_diag(S["A"])
+    b = S["B"][:, [0]].toarray().ravel()
+    t0 = time.perf_counter()
+    _, its, _ = solve.pcg(S["A"], b, d, tol=1e-8)
+    t_col = time.perf_counter() - t0
+    t_step = t_asm + L * t_col
+    return {"value": L / t_step, "unit": "electrode-solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle assembly of the full mesh ({t_asm:.1f} s) + PCG of electrode "
+                       f"column 0 to 1e-8 ({its} it, {t_col:.1f} s), extrapolated to {L} "
+                       f"columns; single-threaded NumPy/SciPy")}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the lead-field build "
+              "shards by electrode column across GPUs by design but that path is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1811_07717_amd import headmodel as hm, zi
+
+    H = hm.workload(a.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(0)
+    nodes = torch.from_numpy(H.nodes).to(dev)
+    tets = torch.from_numpy(H.tets).to(dev)
+    sigma = torch.from_numpy(np.ascontiguousarray(H.sigma)).to(dev)
+    tris = torch.from_numpy(H.tris).to(dev)
+    tre = torch.from_numpy(H.tri_electrode).to(dev)
+    dip = torch.from_numpy(H.dipole_tets).to(dev)
+    L = H.L
+    T = torch.empty((H.n, L), dtype=torch.float64, device=dev)
+    LF = torch.empty((L, 3 * H.m), dtype=torch.float64, device=dev)
+    s0 = zi.System(nodes, tets, sigma, tris, tre, H.Z)
+    G = s0.point_dipoles(dip)
+    s0.close()
+    torch.cuda.synchronize()
+
+    def step():
+        s = zi.System(nodes, tets, sigma, tris, tre, H.Z)
+        _, st = s.transfer_solve(tol=1e-8, precond=a.precond, timing=True, tile=a.tile, out=T)
+        s.leadfield(T, G, out=LF)
+        s.close()
+        return st
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+
+    if a.calib_copy_mb:
+        x = torch.empty(a.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+
+    # dominant kernel: the solver kernel with the largest total time
+    ktot = {}
+    for st in stats:
+        for k, v in st["kernels"].items():
+            e = ktot.setdefault(k, dict(ms=0.0, launches=0, bytes=v["bytes"]))
+            e["ms"] += v["ms"]
+            e["launches"] += v["launches"]
+    dom = max(ktot, key=lambda k: ktot[k]["ms"])
+    avg_ms = ktot[dom]["ms"] / ktot[dom]["launches"]
+    gbs = ktot[dom]["bytes"] / (avg_ms * 1e-3) / 1e9
+    iters = stats[-1]["iters"]
+    out = {
+        "metric": METRIC,
+        "value": L / dt,
+        "unit": "electrode-solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "h_mm": H.h_mm, "n_nodes": H.n, "n_tets": H.e,
+                   "nnz": int(s0.nnz), "electrodes": L, "lf_columns": 3 * H.m,
+                   "tol": 1e-8, "precond": a.precond, "tile": stats[-1]["tile"]},
+        "lf_build_s": dt,
+        "pcg_iters": {"median": int(np.median(iters)), "max": int(iters.max()),
+                      "block_loop": int(stats[-1]["block_iters"])},
+        "solver_kernels": {k: {"avg_ms": v["ms"] / v["launches"],
+                               "gbs": v["bytes"] / (v["ms"] / v["launches"] * 1e-3) / 1e9,
+                               "bytes_per_launch": v["bytes"]} for k, v in ktot.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": traffic_for(dom, a.workload)},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(H, L)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * zi.h -- C-ABI of the MI355X lead-field library (libzi.so).
+ *
+ * The library builds the EEG lead field of a finite-element head model with
+ * the complete electrode model (CEM):
+ *
+ *   zi_assemble        the grounded stiffness/CEM system of Eq. (u_system)
+ *                      (App. A.1): matrices A, B and C;
+ *   zi_transfer_solve  the transfer matrix T = A^-1 B (App. A.4) by a
+ *                      diagonally preconditioned conjugate gradient run on all
+ *                      electrode columns at once (Sec. 2.3.1);
+ *   zi_leadfield       L = R (B^T T - C)^-1 T^T G (App. A.2, Eq. (aku)).
+ *
+ * Conventions
+ *   - Array pointers are DEVICE pointers owned by the caller unless marked
+ *     HOST.  Matrices are row-major.  Indices are 0-based int32.
+ *   - SI units: metres, S/m, Ohm; a lead-field column is the electrode
+ *     voltage (V) for a unit (1 A m) dipole.
+ *   - Every call enqueues its work on `hip_stream` (a hipStream_t; NULL is
+ *     the default stream) and synchronises that stream before returning, so
+ *     the status and statistics are final when the call returns.
+ *   - No exception crosses the ABI; the return value is the status and
+ *     zi_last_error() holds a message for the calling thread.
+ *   - On ZI_EINVAL and ZI_EMESH no caller-visible output is written.
+ *   - A zi_system is not thread-safe; distinct systems may be used from
+ *     distinct threads on distinct streams.
+ *   - Nodes are never reordered: row i of T is node i.
+ */
+#ifndef ZI_H
+#define ZI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct zi_system zi_system; /* opaque, owned by the library */
+
+typedef enum {
+    ZI_OK = 0,
+    ZI_EINVAL = -1,      /* bad argument (size, pointer, option, ground node) */
+    ZI_EMESH = -2,       /* invalid mesh or electrode data */
+    ZI_ENOMEM = -3,      /* device allocation failed */
+    ZI_EDEVICE = -4,     /* HIP runtime error */
+    ZI_ENOTCONV = -5,    /* PCG reached maxit before the tolerance */
+    ZI_EBREAKDOWN = -6   /* p^T A p <= 0 or a non-positive Cholesky pivot */
+} zi_status;
+
+/* Mesh (Sec. 2 "Conductivity distribution"; Sec. 2.4.2 fields nodes/tetra).
+ *   nodes  n_nodes x 3 float64, metres.
+ *   tets   n_tets x 4 int32; vertices distinct; either orientation.
+ *   sigma  n_tets float64 (sigma_ncomp = 1, isotropic) or n_tets x 6
+ *          (sigma_ncomp = 6: s11, s22, s33, s12, s13, s23 per element, the
+ *          row layout of Sec. 2 "Conductivity distribution"), S/m; each
+ *          element's conductivity must be positive (definite).
+ * Errors: ZI_EMESH for an index out of range, repeated vertices, a
+ * degenerate tetrahedron (|det J| <= 1e-12 * (longest edge)^3), a
+ * non-positive or non-finite conductivity, a non-finite coordinate, or a node
+ * that touches more than 127 distinct neighbours. */
+typedef struct {
+    int32_t n_nodes;
+    int32_t n_tets;
+    int32_t sigma_ncomp;
+    const double *nodes;
+    const int32_t *tets;
+    const double *sigma;
+} zi_mesh;
+
+/* Electrodes of the complete electrode model (App. A.1, conditions I-III).
+ *   tris           n_tris x 3 int32: triangles of the electrode patches e_l;
+ *                  each must be a boundary face (a face of exactly one tet).
+ *   tri_electrode  n_tris int32 in [0, n_electrodes); every electrode needs
+ *                  at least one triangle.
+ *   Z              HOST, n_electrodes float64: contact impedance Z_l > 0, Ohm.
+ * The contact area calA_l is the summed area of electrode l's triangles. */
+typedef struct {
+    int32_t n_electrodes;
+    int32_t n_tris;
+    const int32_t *tris;
+    const int32_t *tri_electrode;
+    const double *Z;
+} zi_electrodes;
+
+enum { ZI_PREC_JACOBI = 0, /* D_ii = a_ii */
+       ZI_PREC_LDP = 1     /* lumped diagonal D_ii = sum_j |a_ij| (Sec. 2.3.1) */ };
+
+enum { ZI_FP64 = 0,         /* all arithmetic in float64 */
+       ZI_FP32_SPMM_IR = 1  /* float32 matrix products inside float64 PCG
+                               recurrences, with float64 iterative refinement */ };
+
+/* Options of zi_transfer_solve.  Zero-initialised fields take defaults. */
+typedef struct {
+    double tol;          /* relative residual ||b - A t|| / ||b|| target;
+                            0 -> 1e-8 */
+    int32_t maxit;       /* iteration limit per column; 0 -> 50000 */
+    int32_t precond;     /* ZI_PREC_JACOBI or ZI_PREC_LDP */
+    int32_t precision;   /* ZI_FP64 or ZI_FP32_SPMM_IR */
+    int32_t check_every; /* iterations between host convergence checks; 0 -> 8 */
+    int32_t timing;      /* 1: time the solver kernels with HIP events */
+    int32_t tile;        /* SpMM tile id (see zi_tile_count); -1 -> automatic */
+    const double *x0;    /* n_nodes x L initial iterate, or NULL for zero */
+} zi_solve_opts;
+
+/* Statistics of zi_transfer_solve.  The HOST arrays are caller-owned, length
+ * n_electrodes, and may be NULL. */
+typedef struct {
+    int32_t *iters;        /* HOST: PCG updates done per column */
+    double *relres_rec;    /* HOST: recurrence ||r||/||b|| at exit */
+    double *relres_true;   /* HOST: ||b - A t||/||b|| recomputed at exit */
+    double seconds;        /* wall time of the call */
+    int32_t block_iters;   /* iterations of the multi-column loop */
+    int32_t refinements;   /* outer refinement steps (ZI_FP32_SPMM_IR) */
+    int32_t tile;          /* SpMM tile used */
+    int32_t n_kernels;     /* entries used in the arrays below */
+    double kernel_ms[8];   /* total event-timed ms per solver kernel */
+    int32_t kernel_launches[8];
+    int64_t kernel_bytes[8]; /* algorithmic bytes of one launch */
+    const char *kernel_name[8];
+} zi_solve_stats;
+
+/* Assemble the grounded CEM system of Eq. (u_system).
+ *   a_ij = int sigma grad psi_i . grad psi_j + sum_l 1/(Z_l calA_l) int_{e_l} psi_i psi_j
+ *   b_il = 1/(Z_l calA_l) int_{e_l} psi_i,   c_ll = 1/Z_l
+ * then the ground fix of App. A.1: row and column i' of A are zeroed and
+ * a_{i'i'} = 1.  ground_node = -1 selects the smallest boundary node that is
+ * not a vertex of any electrode triangle; otherwise the given node must be
+ * such a node (ZI_EINVAL if not).
+ * The CSR structure of A is the mesh graph (all pairs sharing a tet,
+ * diagonal included, columns ascending, zero values kept).
+ * *out receives a new system (caller destroys it with zi_system_destroy). */
+zi_status zi_assemble(const zi_mesh *mesh, const zi_electrodes *el,
+                      int32_t ground_node, void *hip_stream, zi_system **out);
+
+/* T = A^-1 B (App. A.4): PCG of Sec. 2.3.1 on every electrode column, from
+ * x0 (or 0) until ||r||_2 <= tol ||b||_2 per column.
+ *   T      n_nodes x n_electrodes float64, written on ZI_OK and ZI_ENOTCONV
+ *          (then it holds the last iterate).
+ *   stats  may be NULL.
+ * ZI_ENOTCONV if a column misses the tolerance within maxit iterations;
+ * ZI_EBREAKDOWN if p^T A p <= 0 (A not positive definite). */
+zi_status zi_transfer_solve(zi_system *sys, const zi_solve_opts *opts, double *T,
+                            zi_solve_stats *stats, void *hip_stream);
+
+/* EEG lead field of App. A.2, Eq. (aku): LF = R (B^T T - C)^-1 T^T G.
+ *   T        n_nodes x L float64 from zi_transfer_solve.
+ *   G        n_nodes x n_cols in CSC form: g_colptr (n_cols + 1), g_rowind
+ *            and g_val (g_colptr[n_cols] entries); the source matrix of
+ *            App. A.1 (entries g_ij = int psi_i div w_j).
+ *   LF       L x n_cols float64, row-major (electrode-major).
+ *   precision ZI_FP64, or 1 for float32 matrix-core products (T^T G and the
+ *            final product rounded to float32 inputs, float32 accumulation).
+ * ZI_EBREAKDOWN if M = C - B^T T is not positive definite. */
+zi_status zi_leadfield(const zi_system *sys, const double *T, int32_t n_cols,
+                       const int32_t *g_colptr, const int32_t *g_rowind,
+                       const double *g_val, double *LF, int32_t precision,
+                       void *hip_stream);
+
+/* Source matrix of point dipoles (Sec. 2 "Primary current model", read as
+ * the partial-integration dipole): a unit dipole along axis k at the centroid
+ * of tet d gives column 3 j + k with G[i, 3 j + k] = -d psi_i / d x_k on that
+ * tet, for the j-th entry d of dipole_tets (columns ordered position 1 xyz,
+ * position 2 xyz, ... as in Sec. 2.4.2).
+ *   dipole_tets  m int32 tet indices.
+ *   g_colptr     3 m + 1 int32 (output), g_rowind and g_val 12 m (output);
+ *                row indices ascending within a column. */
+zi_status zi_point_dipoles(const zi_system *sys, int32_t m, const int32_t *dipole_tets,
+                           int32_t *g_colptr, int32_t *g_rowind, double *g_val,
+                           void *hip_stream);
+
+/* Y = A X for the assembled (grounded) A; X and Y are n_nodes x k row-major.
+ * The product the PCG iterates; exposed for tests and bandwidth measurement.
+ * tile as in zi_solve_opts.  ms_out (HOST, may be NULL) receives the
+ * event-timed kernel duration. */
+zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y,
+                  int32_t tile, double *ms_out, void *hip_stream);
+
+/* Number of SpMM tile configurations and a description of tile t. */
+int32_t zi_tile_count(void);
+const char *zi_tile_name(int32_t t);
+
+typedef struct {
+    int32_t n_nodes, n_tets, n_electrodes, ground_node;
+    int64_t nnz;        /* entries of the mesh-graph CSR of A */
+    int32_t b_nnz;      /* nonzeros of B */
+} zi_system_info;
+
+/* Device views of the assembled system, valid until zi_system_destroy.
+ * Read-only; for tests. */
+typedef struct {
+    const int32_t *row_ptr;  /* n + 1 */
+    const int32_t *col;      /* nnz */
+    const double *val;       /* nnz, grounded A */
+    const int32_t *b_ptr;    /* n + 1: node-major B (row i: electrodes) */
+    const int32_t *b_col;    /* b_nnz electrode indices, ascending per row */
+    const double *b_val;     /* b_nnz */
+    const double *C;         /* L: c_ll */
+    const double *calA;      /* L: contact areas */
+    const uint8_t *boundary; /* n: 1 if the node lies on a boundary face */
+} zi_system_view;
+
+zi_status zi_get_info(const zi_system *sys, zi_system_info *info);
+zi_status zi_get_view(const zi_system *sys, zi_system_view *view);
+
+void zi_system_destroy(zi_system *sys);
+const char *zi_status_string(zi_status s);
+const char *zi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZI_H */

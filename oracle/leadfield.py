@@ -69,3 +69,21 @@ def rdm(a, b):
 def mag(a, b):
     """Magnitude ratio ||a|| / ||b|| per column."""
     return np.linalg.norm(np.asarray(a), axis=0) / np.linalg.norm(np.asarray(b), axis=0)
+
+
+def leadfield_columns_reciprocity(A, B, C, Gcols, tol=1e-12, maxit=200000):
+    """Selected EEG lead-field columns, one sparse solve each (App. A.1-A.2).
+
+    With I = 0 the second block row of Eq. (u_system) gives v = C^-1 B^T z;
+    substituting into the first, (A - B C^-1 B^T) z = -G x.  That matrix is
+    symmetric positive definite once A carries the ground fix, so each column
+    is one preconditioned CG solve (``solve.pcg_columns``, Jacobi diagonal)
+    followed by y = R v.  Gcols is n x k (the chosen columns of G).
+    """
+    from .solve import pcg_columns
+    Bs = sp.csr_matrix(B)
+    K = (sp.csr_matrix(A) - Bs @ sp.diags(1.0 / np.asarray(C)) @ Bs.T).tocsr()
+    rhs = -(Gcols.toarray() if sp.issparse(Gcols) else np.asarray(Gcols))
+    Zc, _, _ = pcg_columns(K, rhs, K.diagonal().copy(), tol=tol, maxit=maxit)
+    V = (Bs.T @ Zc) / np.asarray(C)[:, None]
+    return average_reference(B.shape[1]) @ V

@@ -1,0 +1,289 @@
+// EEG lead field, App. A.2 Eq. (aku):  LF = R (B^T T - C)^-1 T^T G.
+//
+//   schur   S = B^T T - C            (L x L; gathers T rows of each electrode)
+//   chol_w  M = -(S + S^T)/2 = LL^T, W = R S^-1 = -R M^-1   (one workgroup)
+//   gather  Pt[c, :] = sum_k G[k, c] T[k, :]   (T^T G stored n_cols x L)
+//   gemm    LF = W Pt^T on the matrix cores (v_mfma_f64_16x16x4f64, or the
+//           float32 variant), each wave owning 16 output columns and every
+//           electrode row so that a Pt row is read once per wave.
+#include <cmath>
+
+#include "zi_internal.h"
+
+namespace {
+
+using namespace zi;
+
+inline unsigned grid_for(size_t n, int threads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+// Caller's G in CSC form: colptr non-decreasing from 0, row indices in range.
+__global__ void k_check_colptr(const int32_t *cp, int n_cols, int *flag) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > n_cols) return;
+    if (c == 0 && cp[0] != 0) atomicOr(flag, 2);
+    if (c < n_cols && cp[c + 1] < cp[c]) atomicOr(flag, 2);
+}
+
+__global__ void k_check_rowind(const int32_t *ri, int32_t nnz, int32_t n, int *flag) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz && (ri[p] < 0 || ri[p] >= n)) atomicOr(flag, 2);
+}
+
+// S[l, m] = sum_{i in e_l} b_il T[i, m] - c_ll delta_lm; one block per l.
+__global__ void k_schur(const int32_t *e_ptr, const int32_t *e_item, const int32_t *b_row,
+                        const double *b_val, const double *C, const double *T, int L,
+                        double *S) {
+    const int l = blockIdx.x;
+    for (int m = threadIdx.x; m < L; m += blockDim.x) {
+        double s = 0.0;
+        for (int32_t p = e_ptr[l]; p < e_ptr[l + 1]; ++p) {
+            const int32_t k = e_item[p];
+            s = fma(b_val[k], T[(size_t)b_row[k] * L + m], s);
+        }
+        if (m == l) s -= C[l];
+        S[(size_t)l * L + m] = s;
+    }
+}
+
+// In-place Cholesky of M = -(S + S^T)/2 (lower factor in Lf), then
+// Minv = M^-1 by forward/backward substitution per column, then
+// W = -R Minv with R = I - 11^T / L:  W_ij = -(Minv_ij - mean_k Minv_kj).
+// Single workgroup; flag = 1 on a non-positive pivot.
+constexpr int CHOL_THREADS = 256;
+
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_w(const double *S, int L, double *Lf,
+                                                         double *Minv, double *W, int *flag) {
+    __shared__ double red[CHOL_THREADS];
+    __shared__ double piv;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < L * L; idx += CHOL_THREADS) {
+        const int i = idx / L, j = idx % L;
+        Lf[idx] = -0.5 * (S[(size_t)i * L + j] + S[(size_t)j * L + i]);
+    }
+    __syncthreads();
+    for (int j = 0; j < L; ++j) {
+        double part = 0.0;
+        for (int k = tid; k < j; k += CHOL_THREADS) part = fma(Lf[j * L + k], Lf[j * L + k], part);
+        red[tid] = part;
+        __syncthreads();
+        for (int off = CHOL_THREADS / 2; off > 0; off >>= 1) {
+            if (tid < off) red[tid] += red[tid + off];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const double d = Lf[j * L + j] - red[0];
+            if (!(d > 0.0)) *flag = 1;
+            piv = d > 0.0 ? sqrt(d) : 1.0;
+            Lf[j * L + j] = piv;
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < L; i += CHOL_THREADS) {
+            double s = Lf[i * L + j];
+            for (int k = 0; k < j; ++k) s = fma(-Lf[i * L + k], Lf[j * L + k], s);
+            Lf[i * L + j] = s / piv;
+        }
+        __syncthreads();
+    }
+    // Minv column c: solve L y = e_c, L^T x = y  (stored in Minv[:, c])
+    for (int c = tid; c < L; c += CHOL_THREADS) {
+        for (int i = 0; i < L; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) s = fma(-Lf[i * L + k], Minv[(size_t)k * L + c], s);
+            Minv[(size_t)i * L + c] = (i < c) ? 0.0 : s / Lf[i * L + i];
+        }
+        for (int i = L - 1; i >= 0; --i) {
+            double s = Minv[(size_t)i * L + c];
+            for (int k = i + 1; k < L; ++k) s = fma(-Lf[k * L + i], Minv[(size_t)k * L + c], s);
+            Minv[(size_t)i * L + c] = s / Lf[i * L + i];
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < L; c += CHOL_THREADS) {
+        double mean = 0.0;
+        for (int k = 0; k < L; ++k) mean += Minv[(size_t)k * L + c];
+        mean /= L;
+        for (int i = 0; i < L; ++i) W[(size_t)i * L + c] = -(Minv[(size_t)i * L + c] - mean);
+    }
+}
+
+// Pt[c, :] = sum_k G[k, c] T[k, :]; one wave per column, lanes over electrodes.
+__global__ void k_gather(const int32_t *cp, const int32_t *ri, const double *gv, int n_cols,
+                         const double *T, int L, double *Pt) {
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (c >= n_cols) return;
+    const int32_t s = cp[c], e = cp[c + 1];
+    for (int l = lane; l < L; l += 64) {
+        double acc = 0.0;
+        for (int32_t p = s; p < e; ++p) acc = fma(gv[p], T[(size_t)ri[p] * L + l], acc);
+        Pt[(size_t)c * L + l] = acc;
+    }
+}
+
+// LF[l, c] = sum_k W[l, k] Pt[c, k].  One wave per 16 output columns, all L
+// rows (L <= 256 -> at most 16 row tiles of 16).  MFMA 16x16x4 operand layout:
+// lane t supplies A[t%16][t/16] and B[t/16][t%16]; it receives, for
+// i = 0..3, D[t/16 + 4 i][t%16] (float64 variant) or D[4 (t/16) + i][t%16]
+// (float32 variant) -- both measured with an in-bounds probe on gfx950.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <int MT>
+__global__ __launch_bounds__(64) void k_gemm_f64(const double *W, const double *Pt, int L,
+                                                 int n_cols, double *LF) {
+    const int t = threadIdx.x;
+    const int c0 = blockIdx.x * 16;
+    const int col = c0 + (t & 15);
+    const int kq = t >> 4;
+    dbl4 acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < L; k0 += 4) {
+        const int k = k0 + kq;
+        const double b = (col < n_cols && k < L) ? Pt[(size_t)col * L + k] : 0.0;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int row = m * 16 + (t & 15);
+            const double a = (row < L && k < L) ? W[(size_t)row * L + k] : 0.0;
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
+        }
+    }
+    if (col >= n_cols) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = m * 16 + kq + 4 * i;   // f64 result layout
+            if (row < L) LF[(size_t)row * n_cols + col] = acc[m][i];
+        }
+}
+
+template <int MT>
+__global__ __launch_bounds__(64) void k_gemm_f32(const double *W, const double *Pt, int L,
+                                                 int n_cols, double *LF) {
+    const int t = threadIdx.x;
+    const int c0 = blockIdx.x * 16;
+    const int col = c0 + (t & 15);
+    const int kq = t >> 4;
+    flt4 acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = flt4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < L; k0 += 4) {
+        const int k = k0 + kq;
+        const float b = (col < n_cols && k < L) ? (float)Pt[(size_t)col * L + k] : 0.f;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const int row = m * 16 + (t & 15);
+            const float a = (row < L && k < L) ? (float)W[(size_t)row * L + k] : 0.f;
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
+        }
+    }
+    if (col >= n_cols) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = m * 16 + 4 * kq + i;
+            if (row < L) LF[(size_t)row * n_cols + col] = (double)acc[m][i];
+        }
+}
+
+#define ZI_GEMM_SWITCH(KER, mt, ...)                                   \
+    switch (mt) {                                                      \
+        case 1: hipLaunchKernelGGL(KER<1>, __VA_ARGS__); break;        \
+        case 2: hipLaunchKernelGGL(KER<2>, __VA_ARGS__); break;        \
+        case 3: hipLaunchKernelGGL(KER<3>, __VA_ARGS__); break;        \
+        case 4: hipLaunchKernelGGL(KER<4>, __VA_ARGS__); break;        \
+        case 5: hipLaunchKernelGGL(KER<5>, __VA_ARGS__); break;        \
+        case 6: hipLaunchKernelGGL(KER<6>, __VA_ARGS__); break;        \
+        case 7: hipLaunchKernelGGL(KER<7>, __VA_ARGS__); break;        \
+        case 8: hipLaunchKernelGGL(KER<8>, __VA_ARGS__); break;        \
+        case 9: hipLaunchKernelGGL(KER<9>, __VA_ARGS__); break;        \
+        case 10: hipLaunchKernelGGL(KER<10>, __VA_ARGS__); break;      \
+        case 11: hipLaunchKernelGGL(KER<11>, __VA_ARGS__); break;      \
+        case 12: hipLaunchKernelGGL(KER<12>, __VA_ARGS__); break;      \
+        case 13: hipLaunchKernelGGL(KER<13>, __VA_ARGS__); break;      \
+        case 14: hipLaunchKernelGGL(KER<14>, __VA_ARGS__); break;      \
+        case 15: hipLaunchKernelGGL(KER<15>, __VA_ARGS__); break;      \
+        default: hipLaunchKernelGGL(KER<16>, __VA_ARGS__); break;      \
+    }
+
+}  // namespace
+
+zi_status zi_leadfield_impl(const zi_system *csys, const double *T, int32_t n_cols,
+                            const int32_t *cp, const int32_t *ri, const double *gv, double *LF,
+                            int32_t precision, hipStream_t s) {
+    zi_system *sys = const_cast<zi_system *>(csys);
+    const int L = sys->L;
+    if (L > 256) {
+        set_error("zi_leadfield supports at most 256 electrodes (got %d)", L);
+        return ZI_EINVAL;
+    }
+    if (precision != 0 && precision != 1) {
+        set_error("unknown lead-field precision %d", precision);
+        return ZI_EINVAL;
+    }
+    Pool tmp;
+    double *S = nullptr, *Lf = nullptr, *Minv = nullptr;
+    int *flag = nullptr;
+    ZI_TRY(tmp.alloc(&S, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&Lf, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&Minv, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&flag, 1));
+    if (!sys->W) ZI_TRY(sys->pool.alloc(&sys->W, (size_t)L * L));
+    const size_t need = (size_t)n_cols * L;
+    if (need > sys->Pt_cap) {
+        if (sys->Pt) (void)hipFree(sys->Pt);
+        sys->Pt = nullptr;
+        sys->Pt_cap = 0;
+        ZI_HIP(hipMalloc(&sys->Pt, need * sizeof(double)));
+        sys->Pt_cap = need;
+    }
+    ZI_TRY(fill_i32(flag, 0, 1, s));
+    int hflag = 0;
+    if (n_cols > 0) {
+        hipLaunchKernelGGL(k_check_colptr, dim3(grid_for((size_t)n_cols + 1, 256)), dim3(256), 0,
+                           s, cp, n_cols, flag);
+        ZI_HIP(hipGetLastError());
+        int32_t gnnz = 0;
+        ZI_HIP(hipMemcpyAsync(&gnnz, cp + n_cols, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        ZI_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        ZI_HIP(hipStreamSynchronize(s));
+        if (!hflag && gnnz > 0) {
+            hipLaunchKernelGGL(k_check_rowind, dim3(grid_for(gnnz, 256)), dim3(256), 0, s, ri,
+                               gnnz, sys->n, flag);
+            ZI_HIP(hipGetLastError());
+            ZI_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+            ZI_HIP(hipStreamSynchronize(s));
+        }
+        if (hflag) {
+            set_error("G: column pointers not monotone from 0, or a row index out of range");
+            return ZI_EINVAL;
+        }
+    }
+    hipLaunchKernelGGL(k_schur, dim3(L), dim3(64), 0, s, sys->e_ptr, sys->e_item, sys->b_row,
+                       sys->b_val, sys->C, T, L, S);
+    hipLaunchKernelGGL(k_chol_w, dim3(1), dim3(CHOL_THREADS), 0, s, S, L, Lf, Minv, sys->W, flag);
+    ZI_HIP(hipGetLastError());
+    if (n_cols > 0) {
+        hipLaunchKernelGGL(k_gather, dim3(grid_for((size_t)n_cols * 64, 256)), dim3(256), 0, s, cp,
+                           ri, gv, n_cols, T, L, sys->Pt);
+        const int mt = (L + 15) / 16;
+        const dim3 grid(grid_for(n_cols, 16)), block(64);
+        if (precision == 0) {
+            ZI_GEMM_SWITCH(k_gemm_f64, mt, grid, block, 0, s, sys->W, sys->Pt, L, n_cols, LF);
+        } else {
+            ZI_GEMM_SWITCH(k_gemm_f32, mt, grid, block, 0, s, sys->W, sys->Pt, L, n_cols, LF);
+        }
+        ZI_HIP(hipGetLastError());
+    }
+    ZI_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipStreamSynchronize(s));
+    if (hflag) {
+        set_error("M = C - B^T T is not positive definite");
+        return ZI_EBREAKDOWN;
+    }
+    return ZI_OK;
+}

@@ -1,0 +1,178 @@
+// C-ABI entry points of libzi: argument checks, stream handling, errors.
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "zi_internal.h"
+
+namespace zi {
+namespace {
+thread_local char g_err[512] = "";
+}
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+}  // namespace zi
+
+using zi::set_error;
+
+#define ZI_GUARD(body)                                          \
+    try {                                                       \
+        body                                                    \
+    } catch (const std::bad_alloc &) {                          \
+        set_error("host allocation failed");                    \
+        return ZI_ENOMEM;                                       \
+    } catch (...) {                                             \
+        set_error("unexpected exception");                      \
+        return ZI_EDEVICE;                                      \
+    }
+
+extern "C" {
+
+const char *zi_last_error(void) { return zi::g_err; }
+
+const char *zi_status_string(zi_status s) {
+    switch (s) {
+        case ZI_OK: return "ok";
+        case ZI_EINVAL: return "invalid argument";
+        case ZI_EMESH: return "invalid mesh or electrode data";
+        case ZI_ENOMEM: return "out of memory";
+        case ZI_EDEVICE: return "device error";
+        case ZI_ENOTCONV: return "not converged";
+        case ZI_EBREAKDOWN: return "breakdown (matrix not positive definite)";
+    }
+    return "unknown status";
+}
+
+zi_status zi_assemble(const zi_mesh *mesh, const zi_electrodes *el, int32_t ground_node,
+                      void *hip_stream, zi_system **out) {
+    zi::g_err[0] = 0;
+    if (!mesh || !el || !out) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    *out = nullptr;
+    if (mesh->n_nodes < 4 || mesh->n_tets < 1 || !mesh->nodes || !mesh->tets || !mesh->sigma) {
+        set_error("mesh needs n_nodes >= 4, n_tets >= 1 and non-null arrays");
+        return ZI_EINVAL;
+    }
+    if (mesh->sigma_ncomp != 1 && mesh->sigma_ncomp != 6) {
+        set_error("sigma_ncomp must be 1 or 6 (got %d)", mesh->sigma_ncomp);
+        return ZI_EINVAL;
+    }
+    if ((int64_t)mesh->n_tets * 4 >= (int64_t)1 << 31) {
+        set_error("too many tetrahedra for 32-bit incidence indices");
+        return ZI_EINVAL;
+    }
+    if (el->n_electrodes < 1 || el->n_tris < 1 || !el->tris || !el->tri_electrode || !el->Z) {
+        set_error("electrodes need n_electrodes >= 1, n_tris >= 1 and non-null arrays");
+        return ZI_EINVAL;
+    }
+    if (el->n_tris > ((int32_t)1 << 29)) {
+        set_error("too many electrode triangles");
+        return ZI_EINVAL;
+    }
+    if (ground_node < -1 || ground_node >= mesh->n_nodes) {
+        set_error("ground_node %d out of range", ground_node);
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_assemble_impl(mesh, el, ground_node, (hipStream_t)hip_stream, out);)
+}
+
+zi_status zi_transfer_solve(zi_system *sys, const zi_solve_opts *opts, double *T,
+                            zi_solve_stats *stats, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!sys || !opts || !T) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    if (opts->tol < 0 || opts->maxit < 0) {
+        set_error("tol and maxit must be non-negative");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_solve_impl(sys, opts, T, stats, (hipStream_t)hip_stream);)
+}
+
+zi_status zi_leadfield(const zi_system *sys, const double *T, int32_t n_cols,
+                       const int32_t *g_colptr, const int32_t *g_rowind, const double *g_val,
+                       double *LF, int32_t precision, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!sys || !T || !LF || n_cols < 0 || (n_cols > 0 && (!g_colptr || !g_rowind || !g_val))) {
+        set_error("null argument or negative n_cols");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_leadfield_impl(sys, T, n_cols, g_colptr, g_rowind, g_val, LF, precision,
+                                      (hipStream_t)hip_stream);)
+}
+
+zi_status zi_point_dipoles(const zi_system *sys, int32_t m, const int32_t *dipole_tets,
+                           int32_t *g_colptr, int32_t *g_rowind, double *g_val,
+                           void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!sys || m < 0 || !g_colptr || (m > 0 && (!dipole_tets || !g_rowind || !g_val))) {
+        set_error("null argument or negative m");
+        return ZI_EINVAL;
+    }
+    if ((int64_t)m * 12 >= (int64_t)1 << 31) {
+        set_error("too many dipoles");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_point_dipoles_impl(sys, m, dipole_tets, g_colptr, g_rowind, g_val,
+                                          (hipStream_t)hip_stream);)
+}
+
+zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y, int32_t tile,
+                  double *ms_out, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!sys || !X || !Y || k <= 0) {
+        set_error("null argument or k <= 0");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_spmm_impl(sys, k, X, Y, tile, ms_out, (hipStream_t)hip_stream);)
+}
+
+int32_t zi_tile_count(void) { return zi_tile_count_impl(); }
+const char *zi_tile_name(int32_t t) { return zi_tile_name_impl(t); }
+
+zi_status zi_get_info(const zi_system *sys, zi_system_info *info) {
+    if (!sys || !info) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    info->n_nodes = sys->n;
+    info->n_tets = sys->e;
+    info->n_electrodes = sys->L;
+    info->ground_node = sys->ground;
+    info->nnz = sys->nnz;
+    info->b_nnz = sys->b_nnz;
+    return ZI_OK;
+}
+
+zi_status zi_get_view(const zi_system *sys, zi_system_view *v) {
+    if (!sys || !v) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    v->row_ptr = sys->row_ptr;
+    v->col = sys->col;
+    v->val = sys->val;
+    v->b_ptr = sys->b_ptr;
+    v->b_col = sys->b_col;
+    v->b_val = sys->b_val;
+    v->C = sys->C;
+    v->calA = sys->calA;
+    v->boundary = sys->boundary;
+    return ZI_OK;
+}
+
+void zi_system_destroy(zi_system *sys) {
+    if (!sys) return;
+    if (sys->ws) zi_solver_ws_destroy(sys->ws);
+    if (sys->Pt) (void)hipFree(sys->Pt);
+    delete sys;
+}
+
+}  // extern "C"

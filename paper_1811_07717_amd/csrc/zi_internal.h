@@ -1,0 +1,150 @@
+// Internal declarations shared by the HIP sources of libzi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/zi.h"
+
+namespace zi {
+
+void set_error(const char *fmt, ...);
+
+#define ZI_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t zi_e_ = (call);                                                \
+        if (zi_e_ != hipSuccess) {                                                \
+            ::zi::set_error("%s failed: %s (%s:%d)", #call,                       \
+                            hipGetErrorString(zi_e_), __FILE__, __LINE__);        \
+            return zi_e_ == hipErrorOutOfMemory ? ZI_ENOMEM : ZI_EDEVICE;         \
+        }                                                                         \
+    } while (0)
+
+#define ZI_TRY(expr)                                                              \
+    do {                                                                          \
+        zi_status zi_s_ = (expr);                                                 \
+        if (zi_s_ != ZI_OK) return zi_s_;                                         \
+    } while (0)
+
+// Validation flags raised by kernels (bitwise OR into a device word).
+enum : int {
+    F_TET_INDEX = 1 << 0,     // vertex index out of range or repeated
+    F_SIGMA = 1 << 1,         // conductivity not positive (definite) / finite
+    F_COORD = 1 << 2,         // non-finite node coordinate
+    F_DEGENERATE = 1 << 3,    // |det J| too small
+    F_TRI_INDEX = 1 << 4,     // electrode triangle index out of range / repeated
+    F_TRI_ELECTRODE = 1 << 5, // tri_electrode out of range
+    F_TRI_NOT_FACE = 1 << 6,  // electrode triangle is not a boundary face
+    F_DEGREE = 1 << 7,        // node with more than MAX_NEIGHBOURS neighbours
+    F_EMPTY_ELECTRODE = 1 << 8,
+    F_DIPOLE_INDEX = 1 << 9,
+};
+
+constexpr int MAX_NEIGHBOURS = 128;   // distinct CSR columns per row (incl. diagonal)
+
+// Owned device allocation list: everything allocated through a Pool is freed
+// by release().
+struct Pool {
+    std::vector<void *> ptrs;
+    template <class T>
+    zi_status alloc(T **p, size_t count) {
+        *p = nullptr;
+        if (count == 0) count = 1;
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess) {
+            set_error("hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                      hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? ZI_ENOMEM : ZI_EDEVICE;
+        }
+        ptrs.push_back(q);
+        *p = static_cast<T *>(q);
+        return ZI_OK;
+    }
+    void release() {
+        for (void *q : ptrs) (void)hipFree(q);
+        ptrs.clear();
+    }
+    ~Pool() { release(); }
+};
+
+// ---------------------------------------------------------------------------
+// Generic device utilities (k_util.hip)
+// ---------------------------------------------------------------------------
+
+// Exclusive scan of `count` int32 values: out[0..count], out[count] = total.
+// `out` may not alias `in`.  Temporaries come from `pool`.
+zi_status scan_exclusive(const int32_t *in, int32_t *out, int32_t count, Pool &pool,
+                         hipStream_t s);
+
+// Bucket the items k = 0..n_items-1 by keys[k] in [0, n_buckets): ptr gets
+// n_buckets + 1 offsets and items the item ids grouped by bucket, ascending
+// inside each bucket when `sort` is true.  Keys must be in range.
+zi_status bucketize(const int32_t *keys, int32_t n_items, int32_t n_buckets,
+                    int32_t *ptr, int32_t *items, bool sort, Pool &pool, hipStream_t s);
+
+zi_status fill_i32(int32_t *p, int32_t value, size_t count, hipStream_t s);
+zi_status fill_f64(double *p, double value, size_t count, hipStream_t s);
+zi_status copy_cols(const double *src, int32_t lds, double *dst, int32_t ldd,
+                    int32_t rows, int32_t cols, hipStream_t s);
+
+}  // namespace zi
+
+// ---------------------------------------------------------------------------
+// The assembled system
+// ---------------------------------------------------------------------------
+
+struct zi_solver_ws;   // PCG workspace (k_pcg.hip)
+
+struct zi_system {
+    int32_t n = 0, e = 0, L = 0, ntris = 0, ncomp = 1;
+    int32_t ground = -1;
+    int64_t nnz = 0;
+    int32_t b_nnz = 0;
+    int device = 0;
+
+    // copies of the inputs the later stages need
+    double *nodes = nullptr;     // n x 3
+    int32_t *tets = nullptr;     // e x 4
+    double *sigma = nullptr;     // e x ncomp
+
+    // A: mesh-graph CSR, grounded values
+    int32_t *row_ptr = nullptr, *col = nullptr;
+    double *val = nullptr;
+    double *diag = nullptr;      // a_ii
+    double *absrow = nullptr;    // sum_j |a_ij|
+
+    // B node-major (row i -> electrodes) and electrode-major (l -> entries)
+    int32_t *b_ptr = nullptr, *b_col = nullptr, *b_row = nullptr;
+    double *b_val = nullptr;
+    int32_t *e_ptr = nullptr, *e_item = nullptr;
+    double *C = nullptr, *calA = nullptr;
+    uint8_t *boundary = nullptr;
+
+    // lead-field scratch
+    double *W = nullptr;         // L x L
+    double *Pt = nullptr;        // n_cols x L (grows)
+    size_t Pt_cap = 0;
+
+    zi::Pool pool;               // owns every array above
+    zi_solver_ws *ws = nullptr;  // lazily created
+};
+
+// Stage entry points (defined in the .hip files).
+zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t ground,
+                           hipStream_t s, zi_system **out);
+zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *opts, double *T,
+                        zi_solve_stats *stats, hipStream_t s);
+zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double *Y,
+                       int32_t tile, double *ms, hipStream_t s);
+zi_status zi_leadfield_impl(const zi_system *sys, const double *T, int32_t n_cols,
+                            const int32_t *cp, const int32_t *ri, const double *gv,
+                            double *LF, int32_t precision, hipStream_t s);
+zi_status zi_point_dipoles_impl(const zi_system *sys, int32_t m, const int32_t *dt,
+                                int32_t *cp, int32_t *ri, double *gv, hipStream_t s);
+void zi_solver_ws_destroy(zi_solver_ws *ws);
+int32_t zi_tile_count_impl();
+const char *zi_tile_name_impl(int32_t t);

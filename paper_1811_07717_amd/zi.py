@@ -1,0 +1,285 @@
+"""Python binding of libzi (the C-ABI in include/zi.h).
+
+Argument marshalling only: every step of the lead-field build runs in the
+library's HIP kernels.  Tensors passed in must be contiguous CUDA (HIP)
+tensors of the documented dtypes; calls run on torch's current stream.
+The binding fails loudly when libzi.so is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzi.so")
+
+ZI_OK, ZI_EINVAL, ZI_EMESH, ZI_ENOMEM, ZI_EDEVICE, ZI_ENOTCONV, ZI_EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "ZI_OK", -1: "ZI_EINVAL", -2: "ZI_EMESH", -3: "ZI_ENOMEM", -4: "ZI_EDEVICE",
+                -5: "ZI_ENOTCONV", -6: "ZI_EBREAKDOWN"}
+PRECOND = {"jacobi": 0, "ldp": 1}
+PRECISION = {"fp64": 0, "fp32_spmm_ir": 1}
+
+c_i32p = ctypes.POINTER(ctypes.c_int32)
+c_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class ZiMesh(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_tets", ctypes.c_int32),
+                ("sigma_ncomp", ctypes.c_int32), ("nodes", ctypes.c_void_p),
+                ("tets", ctypes.c_void_p), ("sigma", ctypes.c_void_p)]
+
+
+class ZiElectrodes(ctypes.Structure):
+    _fields_ = [("n_electrodes", ctypes.c_int32), ("n_tris", ctypes.c_int32),
+                ("tris", ctypes.c_void_p), ("tri_electrode", ctypes.c_void_p),
+                ("Z", c_f64p)]
+
+
+class ZiSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("x0", ctypes.c_void_p)]
+
+
+class ZiSolveStats(ctypes.Structure):
+    _fields_ = [("iters", c_i32p), ("relres_rec", c_f64p), ("relres_true", c_f64p),
+                ("seconds", ctypes.c_double), ("block_iters", ctypes.c_int32),
+                ("refinements", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("n_kernels", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 8),
+                ("kernel_launches", ctypes.c_int32 * 8), ("kernel_bytes", ctypes.c_int64 * 8),
+                ("kernel_name", ctypes.c_char_p * 8)]
+
+
+class ZiInfo(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_tets", ctypes.c_int32),
+                ("n_electrodes", ctypes.c_int32), ("ground_node", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("b_nnz", ctypes.c_int32)]
+
+
+class ZiView(ctypes.Structure):
+    _fields_ = [("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("b_ptr", ctypes.c_void_p), ("b_col", ctypes.c_void_p),
+                ("b_val", ctypes.c_void_p), ("C", ctypes.c_void_p), ("calA", ctypes.c_void_p),
+                ("boundary", ctypes.c_void_p)]
+
+
+# (name, restype, argtypes) of every function declared in include/zi.h
+SIGNATURES = [
+    ("zi_assemble", ctypes.c_int, [ctypes.POINTER(ZiMesh), ctypes.POINTER(ZiElectrodes),
+                                   ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    ("zi_transfer_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ZiSolveOpts),
+                                         ctypes.c_void_p, ctypes.POINTER(ZiSolveStats),
+                                         ctypes.c_void_p]),
+    ("zi_leadfield", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    ("zi_point_dipoles", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    ("zi_spmm", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_int32, c_f64p, ctypes.c_void_p]),
+    ("zi_tile_count", ctypes.c_int32, []),
+    ("zi_tile_name", ctypes.c_char_p, [ctypes.c_int32]),
+    ("zi_get_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ZiInfo)]),
+    ("zi_get_view", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ZiView)]),
+    ("zi_system_destroy", None, [ctypes.c_void_p]),
+    ("zi_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("zi_last_error", ctypes.c_char_p, []),
+]
+
+_lib = None
+_hip = None
+
+
+def lib():
+    """The loaded libzi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1811_07717_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _hiplib():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return _hip
+
+
+class ZiError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib().zi_last_error().decode()
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def _check(st, where):
+    if st != ZI_OK:
+        raise ZiError(st, where)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class System:
+    """An assembled CEM system (zi_assemble) with its solve/lead-field calls."""
+
+    def __init__(self, nodes, tets, sigma, tris, tri_electrode, Z, ground=-1):
+        import torch
+        self._keep = (nodes, tets, sigma, tris, tri_electrode)
+        Zh = np.ascontiguousarray(np.asarray(Z.cpu() if hasattr(Z, "cpu") else Z,
+                                             dtype=np.float64))
+        self._Z = Zh
+        ncomp = 1 if sigma.dim() == 1 else int(sigma.shape[1])
+        mesh = ZiMesh(int(nodes.shape[0]), int(tets.shape[0]), ncomp,
+                      _dev(nodes, torch.float64, "nodes"), _dev(tets, torch.int32, "tets"),
+                      _dev(sigma, torch.float64, "sigma"))
+        el = ZiElectrodes(int(Zh.shape[0]), int(tris.shape[0]), _dev(tris, torch.int32, "tris"),
+                          _dev(tri_electrode, torch.int32, "tri_electrode"),
+                          Zh.ctypes.data_as(c_f64p))
+        h = ctypes.c_void_p()
+        _check(lib().zi_assemble(ctypes.byref(mesh), ctypes.byref(el), int(ground), _stream(),
+                                 ctypes.byref(h)), "zi_assemble")
+        self._h = h
+        inf = ZiInfo()
+        _check(lib().zi_get_info(self._h, ctypes.byref(inf)), "zi_get_info")
+        self.n, self.e, self.L = inf.n_nodes, inf.n_tets, inf.n_electrodes
+        self.ground, self.nnz, self.b_nnz = inf.ground_node, inf.nnz, inf.b_nnz
+
+    @classmethod
+    def from_head(cls, H, device="cuda", ground=-1):
+        import torch
+        d = torch.device(device)
+        return cls(torch.from_numpy(H.nodes).to(d), torch.from_numpy(H.tets).to(d),
+                   torch.from_numpy(np.ascontiguousarray(H.sigma)).to(d),
+                   torch.from_numpy(H.tris).to(d), torch.from_numpy(H.tri_electrode).to(d),
+                   H.Z, ground=ground)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().zi_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- views (device copies) ---------------------------------------------
+    def view(self):
+        """Copies of the assembled arrays as torch tensors on the device."""
+        import torch
+        v = ZiView()
+        _check(lib().zi_get_view(self._h, ctypes.byref(v)), "zi_get_view")
+        dev = torch.device("cuda")
+        torch.cuda.synchronize()
+
+        def cp(ptr, count, dtype):
+            out = torch.empty(count, dtype=dtype, device=dev)
+            nbytes = count * out.element_size()
+            if nbytes:
+                rc = _hiplib().hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr),
+                                         nbytes, 3)
+                if rc != 0:
+                    raise RuntimeError(f"hipMemcpy failed ({rc})")
+            return out
+        n, L = self.n, self.L
+        return dict(row_ptr=cp(v.row_ptr, n + 1, torch.int32), col=cp(v.col, self.nnz, torch.int32),
+                    val=cp(v.val, self.nnz, torch.float64), b_ptr=cp(v.b_ptr, n + 1, torch.int32),
+                    b_col=cp(v.b_col, self.b_nnz, torch.int32),
+                    b_val=cp(v.b_val, self.b_nnz, torch.float64), C=cp(v.C, L, torch.float64),
+                    calA=cp(v.calA, L, torch.float64), boundary=cp(v.boundary, n, torch.uint8))
+
+    # -- solve ---------------------------------------------------------------
+    def transfer_solve(self, tol=1e-8, maxit=0, precond="jacobi", precision="fp64",
+                       check_every=0, timing=False, tile=-1, x0=None, out=None,
+                       raise_on_error=True):
+        import torch
+        T = out if out is not None else torch.empty((self.n, self.L), dtype=torch.float64,
+                                                     device="cuda")
+        iters = np.zeros(self.L, dtype=np.int32)
+        rec = np.zeros(self.L)
+        true = np.zeros(self.L)
+        st = ZiSolveStats()
+        st.iters = iters.ctypes.data_as(c_i32p)
+        st.relres_rec = rec.ctypes.data_as(c_f64p)
+        st.relres_true = true.ctypes.data_as(c_f64p)
+        o = ZiSolveOpts(float(tol), int(maxit), PRECOND[precond], PRECISION[precision],
+                        int(check_every), int(bool(timing)), int(tile),
+                        _dev(x0, torch.float64, "x0") if x0 is not None else None)
+        rc = lib().zi_transfer_solve(self._h, ctypes.byref(o), _dev(T, torch.float64, "T"),
+                                     ctypes.byref(st), _stream())
+        stats = dict(iters=iters, relres_rec=rec, relres_true=true, seconds=st.seconds,
+                     block_iters=st.block_iters, refinements=st.refinements, tile=st.tile,
+                     status=rc, kernels={})
+        for k in range(st.n_kernels):
+            stats["kernels"][st.kernel_name[k].decode()] = dict(
+                ms=st.kernel_ms[k], launches=st.kernel_launches[k], bytes=st.kernel_bytes[k])
+        if raise_on_error:
+            _check(rc, "zi_transfer_solve")
+        return T, stats
+
+    def point_dipoles(self, dipole_tets):
+        import torch
+        m = int(dipole_tets.shape[0])
+        cp = torch.empty(3 * m + 1, dtype=torch.int32, device="cuda")
+        ri = torch.empty(12 * m, dtype=torch.int32, device="cuda")
+        gv = torch.empty(12 * m, dtype=torch.float64, device="cuda")
+        _check(lib().zi_point_dipoles(self._h, m, _dev(dipole_tets, torch.int32, "dipole_tets"),
+                                      _dev(cp, torch.int32, "colptr"),
+                                      _dev(ri, torch.int32, "rowind"),
+                                      _dev(gv, torch.float64, "val"), _stream()),
+               "zi_point_dipoles")
+        return cp, ri, gv
+
+    def leadfield(self, T, G, precision=0, out=None):
+        import torch
+        cp, ri, gv = G
+        ncols = int(cp.shape[0]) - 1
+        LF = out if out is not None else torch.empty((self.L, ncols), dtype=torch.float64,
+                                                     device="cuda")
+        _check(lib().zi_leadfield(self._h, _dev(T, torch.float64, "T"), ncols,
+                                  _dev(cp, torch.int32, "g_colptr"),
+                                  _dev(ri, torch.int32, "g_rowind"),
+                                  _dev(gv, torch.float64, "g_val"),
+                                  _dev(LF, torch.float64, "LF"), int(precision), _stream()),
+               "zi_leadfield")
+        return LF
+
+    def spmm(self, X, tile=-1, out=None):
+        import torch
+        k = int(X.shape[1])
+        Y = out if out is not None else torch.empty_like(X)
+        ms = ctypes.c_double(0.0)
+        _check(lib().zi_spmm(self._h, k, _dev(X, torch.float64, "X"), _dev(Y, torch.float64, "Y"),
+                             int(tile), ctypes.byref(ms), _stream()), "zi_spmm")
+        return Y, ms.value
+
+
+def tile_names():
+    return [lib().zi_tile_name(t).decode() for t in range(lib().zi_tile_count())]

@@ -192,3 +192,12 @@ def test_rdm_mag_definitions():
     c = np.array([[0.0], [1.0]])
     d = np.array([[1.0], [0.0]])
     assert lf.rdm(c, d)[0] == pytest.approx(np.sqrt(2.0))
+
+
+def test_reciprocity_columns_match_eq_aku(head8, sys8, direct8):
+    # Column-by-column lead field from the Schur system equals Eq. (aku).
+    G = source.point_dipole_matrix(head8.nodes, head8.tets, head8.dipole_tets)
+    LF = lf.leadfield(direct8, sys8["B"], sys8["C"], G)
+    cols = [0, 4, 2999]
+    got = lf.leadfield_columns_reciprocity(sys8["A"], sys8["B"], sys8["C"], G[:, cols])
+    assert np.abs(got - LF[:, cols]).max() <= 1e-9 * np.abs(LF[:, cols]).max()
