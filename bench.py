@@ -36,7 +36,10 @@ def parse():
     p.add_argument("--workload", default="sphere2mm_L128")
     p.add_argument("--tile", type=int, default=-1)
     p.add_argument("--precond", default="jacobi")
+    p.add_argument("--precision", default="fp64", choices=["fp64", "fp32_spmm_ir"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--sweep-tiles", action="store_true",
+                   help="also time zi_spmm with every tile on an n x L block")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="also run one torch copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -114,7 +117,8 @@ def main():
 
     def step():
         s = zi.System(nodes, tets, sigma, tris, tre, H.Z)
-        _, st = s.transfer_solve(tol=1e-8, precond=a.precond, timing=True, tile=a.tile, out=T)
+        _, st = s.transfer_solve(tol=1e-8, precond=a.precond, precision=a.precision,
+                                 timing=True, tile=a.tile, out=T)
         s.leadfield(T, G, out=LF)
         s.close()
         return st
@@ -132,6 +136,19 @@ def main():
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
+
+    tiles = None
+    if a.sweep_tiles:
+        s1 = zi.System(nodes, tets, sigma, tris, tre, H.Z)
+        X = torch.randn((H.n, L + (L & 1)), dtype=torch.float64, device=dev)
+        nb = 12 * s1.nnz_solver + 4 * (H.n + 1) + 16 * H.n * X.shape[1]
+        tiles = {}
+        for t, name in enumerate(zi.tile_names()):
+            Y, _ = s1.spmm(X, tile=t)
+            ms = min(s1.spmm(X, tile=t, out=Y)[1] for _ in range(5))
+            tiles[name] = {"ms": ms, "gbs": nb / (ms * 1e-3) / 1e9}
+        s1.close()
+        del X
 
     # dominant kernel: the solver kernel with the largest total time
     ktot = {}
@@ -155,14 +172,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if a.precision == "fp64" else "f32 products, f64 recurrences",
         "data": "synthetic",
         "config": {"workload": a.workload, "h_mm": H.h_mm, "n_nodes": H.n, "n_tets": H.e,
-                   "nnz": int(s0.nnz), "electrodes": L, "lf_columns": 3 * H.m,
-                   "tol": 1e-8, "precond": a.precond, "tile": stats[-1]["tile"]},
+                   "nnz": int(s0.nnz), "nnz_solver": int(s0.nnz_solver), "electrodes": L, "lf_columns": 3 * H.m,
+                   "tol": 1e-8, "precond": a.precond, "precision": a.precision,
+                   "tile": stats[-1]["tile"]},
         "lf_build_s": dt,
         "pcg_iters": {"median": int(np.median(iters)), "max": int(iters.max()),
-                      "block_loop": int(stats[-1]["block_iters"])},
+                      "block_loop": int(stats[-1]["block_iters"]),
+                      "refinements": int(stats[-1]["refinements"])},
         "solver_kernels": {k: {"avg_ms": v["ms"] / v["launches"],
                                "gbs": v["bytes"] / (v["ms"] / v["launches"] * 1e-3) / 1e9,
                                "bytes_per_launch": v["bytes"]} for k, v in ktot.items()},
@@ -170,6 +189,8 @@ def main():
                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                      "traffic": traffic_for(dom, a.workload)},
     }
+    if tiles:
+        out["spmm_tiles"] = tiles
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(H, L)
     print(json.dumps(out))

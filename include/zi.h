@@ -98,7 +98,10 @@ typedef struct {
     int32_t precision;   /* ZI_FP64 or ZI_FP32_SPMM_IR */
     int32_t check_every; /* iterations between host convergence checks; 0 -> 8 */
     int32_t timing;      /* 1: time the solver kernels with HIP events */
-    int32_t tile;        /* SpMM tile id (see zi_tile_count); -1 -> automatic */
+    int32_t tile;        /* SpMM tile id (see zi_tile_count); -1 -> the tile
+                            zi_autotune chose, else a width-based default */
+    int32_t graph;       /* 1: replay the iteration loop as a hipGraph of
+                            check_every iterations (no per-kernel timing) */
     const double *x0;    /* n_nodes x L initial iterate, or NULL for zero */
 } zi_solve_opts;
 
@@ -142,6 +145,26 @@ zi_status zi_assemble(const zi_mesh *mesh, const zi_electrodes *el,
 zi_status zi_transfer_solve(zi_system *sys, const zi_solve_opts *opts, double *T,
                             zi_solve_stats *stats, void *hip_stream);
 
+/* Transfer matrices of several systems (e.g. many head models) at once.
+ * Each system runs exactly the iteration of zi_transfer_solve; the
+ * iterations of all systems that are still active are captured into one
+ * hipGraph (one branch per system, check_every iterations per replay) that is
+ * replayed until every system has converged.  opts applies to every system
+ * (x0 must be NULL); T[k] is n_nodes(k) x L(k); stats may be NULL or an array
+ * of n_systems.  Returns the first non-OK status of the systems (all T are
+ * written). */
+zi_status zi_transfer_solve_batch(zi_system *const *systems, int32_t n_systems,
+                                  const zi_solve_opts *opts, double *const *T,
+                                  zi_solve_stats *stats, void *hip_stream);
+
+/* Autotuner: times the solver's SpMM (with its p.q epilogue) for every tile
+ * on this system's n x L block in the given precision (ZI_FP64 or
+ * ZI_FP32_SPMM_IR) and stores the fastest; later solves with tile = -1 use
+ * it.  best_tile (HOST, may be NULL) receives it; ms (HOST, may be NULL,
+ * zi_tile_count() entries) the measured milliseconds per tile. */
+zi_status zi_autotune(zi_system *sys, int32_t precision, int32_t *best_tile, double *ms,
+                      void *hip_stream);
+
 /* EEG lead field of App. A.2, Eq. (aku): LF = R (B^T T - C)^-1 T^T G.
  *   T        n_nodes x L float64 from zi_transfer_solve.
  *   G        n_nodes x n_cols in CSC form: g_colptr (n_cols + 1), g_rowind
@@ -168,8 +191,29 @@ zi_status zi_point_dipoles(const zi_system *sys, int32_t m, const int32_t *dipol
                            int32_t *g_colptr, int32_t *g_rowind, double *g_val,
                            void *hip_stream);
 
-/* Y = A X for the assembled (grounded) A; X and Y are n_nodes x k row-major.
- * The product the PCG iterates; exposed for tests and bandwidth measurement.
+/* Source matrix of the linearized EIT lead field (App. A.3).
+ * With current patterns I (HOST, L x n_patterns row-major; every pattern must
+ * sum to zero, the grounding condition of App. A.1), M = C - B^T T and
+ * U = T M^-1 I, column p * n_elems + j of the output CSC matrix holds
+ * K1_m U[:, p] on the four vertices of tet m = elems[j] (ascending rows),
+ * where K1_m = dA/ds_m is the element stiffness matrix of tet m for unit
+ * conductivity.  zi_leadfield(sys, T, n_patterns * n_elems, <this G>, ...)
+ * then returns dy/ds_m = -R M^-1 T^T K1_m U, the linearized EIT lead field.
+ *   T         n_nodes x L from zi_transfer_solve.
+ *   elems     n_elems int32 tet indices (device), or NULL for every tet
+ *             (n_elems must then equal n_tets).
+ *   g_colptr  n_patterns * n_elems + 1; g_rowind, g_val 4 * n_patterns * n_elems.
+ *   y_bg      HOST L x n_patterns (may be NULL): background data R M^-1 I.
+ * ZI_EINVAL for an index out of range or a pattern not summing to zero;
+ * ZI_EBREAKDOWN if M is not positive definite. */
+zi_status zi_eit_source(const zi_system *sys, const double *T, int32_t n_patterns,
+                        const double *I, int32_t n_elems, const int32_t *elems,
+                        int32_t *g_colptr, int32_t *g_rowind, double *g_val, double *y_bg,
+                        void *hip_stream);
+
+/* Y = A X for the assembled (grounded) A; X and Y are n_nodes x k row-major,
+ * k even.  The product the PCG iterates (the solver's copy of A, see
+ * zi_system_info.nnz_solver); exposed for tests and bandwidth measurement.
  * tile as in zi_solve_opts.  ms_out (HOST, may be NULL) receives the
  * event-timed kernel duration. */
 zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y,
@@ -183,6 +227,9 @@ typedef struct {
     int32_t n_nodes, n_tets, n_electrodes, ground_node;
     int64_t nnz;        /* entries of the mesh-graph CSR of A */
     int32_t b_nnz;      /* nonzeros of B */
+    int64_t nnz_solver; /* entries the solver streams: A without the
+                           off-diagonal entries |a_ij| <= 64 eps sqrt(a_ii a_jj),
+                           which lie below the assembly's own rounding error */
 } zi_system_info;
 
 /* Device views of the assembled system, valid until zi_system_destroy.

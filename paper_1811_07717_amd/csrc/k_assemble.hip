@@ -453,6 +453,43 @@ __global__ void k_diags(const int32_t *row_ptr, const int32_t *col, const double
     absrow[i] = s;
 }
 
+// Solver copy of A: off-diagonal entries with |a_ij| <= DROP sqrt(|a_ii a_jj|)
+// are left out.  DROP = 64 eps is below the rounding error of the assembly
+// itself (each entry is a sum of a few element contributions of size ~a_ii),
+// so such entries are indistinguishable from zero: on Kuhn meshes with
+// isotropic conductivity they are the couplings that vanish exactly in real
+// arithmetic and come out as ~1e-17 a_ii in floating point.
+constexpr double DROP = 64.0 * 2.220446049250313e-16;
+
+__device__ __forceinline__ bool keep_entry(int64_t i, int32_t j, double v, const double *diag) {
+    if (j == i) return true;
+    return fabs(v) > DROP * sqrt(fabs(diag[i] * diag[j]));
+}
+
+__global__ void k_nz_count(const int32_t *row_ptr, const int32_t *col, const double *val,
+                           const double *diag, int32_t n, int32_t *len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cnt = 0;
+    for (int32_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) cnt += keep_entry(i, col[q], val[q], diag);
+    len[i] = cnt;
+}
+
+__global__ void k_nz_fill(const int32_t *row_ptr, const int32_t *col, const double *val,
+                          const double *diag, int32_t n, const int32_t *sp_ptr, int32_t *sp_col,
+                          double *sp_val) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t o = sp_ptr[i];
+    for (int32_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+        if (keep_entry(i, col[q], val[q], diag)) {
+            sp_col[o] = col[q];
+            sp_val[o] = val[q];
+            ++o;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // point-dipole source matrix
 // ---------------------------------------------------------------------------
@@ -489,6 +526,45 @@ __global__ void k_point_dipoles(const double *nodes, const int32_t *tets, const 
         }
     }
     if (j == m - 1) cp[3 * m] = (int32_t)(12 * m);
+}
+
+// Source matrix of the linearized EIT lead field (App. A.3): column
+// p * ne + j holds K1_m U[:, p] on the vertices of tet m = elems[j] (ascending
+// rows), K1_m the unit-conductivity element matrix, U = T M^-1 I (n x P).
+__global__ void k_eit_columns(const double *nodes, const int32_t *tets, const int32_t *elems,
+                              int32_t ne, int32_t P, const double *U, int32_t *cp, int32_t *ri,
+                              double *gv) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)ne * P) return;
+    const int p = (int)(idx / ne);
+    const int64_t j = idx - (int64_t)p * ne;
+    const int64_t m = elems ? elems[j] : j;
+    V3 g[4];
+    bool degenerate;
+    const double det = tet_gradients(nodes, tets, m, g, &degenerate);
+    const double vol = fabs(det) / 6.0;
+    double u[4], w[4];
+    for (int a = 0; a < 4; ++a) u[a] = U[(size_t)tets[4 * m + a] * P + p];
+    for (int a = 0; a < 4; ++a) {
+        double acc = 0.0;
+        for (int b = 0; b < 4; ++b) acc += vol * dot(g[a], g[b]) * u[b];
+        w[a] = acc;
+    }
+    int ord[4] = {0, 1, 2, 3};
+    for (int a = 1; a < 4; ++a) {
+        int x = ord[a], b = a - 1;
+        while (b >= 0 && tets[4 * m + ord[b]] > tets[4 * m + x]) {
+            ord[b + 1] = ord[b];
+            --b;
+        }
+        ord[b + 1] = x;
+    }
+    cp[idx] = (int32_t)(4 * idx);
+    for (int a = 0; a < 4; ++a) {
+        ri[4 * idx + a] = tets[4 * m + ord[a]];
+        gv[4 * idx + a] = w[ord[a]];
+    }
+    if (idx == (int64_t)ne * P - 1) cp[(int64_t)ne * P] = (int32_t)(4 * (int64_t)ne * P);
 }
 
 // ---------------------------------------------------------------------------
@@ -730,6 +806,22 @@ zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t
     hipLaunchKernelGGL(k_diags, dim3(grid_for(n, 256)), dim3(256), 0, s, sys->row_ptr, sys->col,
                        sys->val, n, sys->diag, sys->absrow);
     ZI_HIP(hipGetLastError());
+    int32_t *splen = nullptr;
+    ZI_TRY(tmp.alloc(&splen, (size_t)n));
+    ZI_TRY(P.alloc(&sys->sp_ptr, (size_t)n + 1));
+    hipLaunchKernelGGL(k_nz_count, dim3(grid_for(n, 256)), dim3(256), 0, s, sys->row_ptr, sys->col,
+                       sys->val, sys->diag, n, splen);
+    ZI_HIP(hipGetLastError());
+    ZI_TRY(scan_exclusive(splen, sys->sp_ptr, n, tmp, s));
+    int32_t spnnz = 0;
+    ZI_HIP(hipMemcpyAsync(&spnnz, sys->sp_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipStreamSynchronize(s));
+    sys->sp_nnz = spnnz;
+    ZI_TRY(P.alloc(&sys->sp_col, (size_t)spnnz));
+    ZI_TRY(P.alloc(&sys->sp_val, (size_t)spnnz));
+    hipLaunchKernelGGL(k_nz_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, sys->row_ptr, sys->col,
+                       sys->val, sys->diag, n, sys->sp_ptr, sys->sp_col, sys->sp_val);
+    ZI_HIP(hipGetLastError());
     ZI_HIP(hipStreamSynchronize(s));
     tmp.release();
     guard.p = nullptr;
@@ -759,5 +851,30 @@ zi_status zi_point_dipoles_impl(const zi_system *sys, int32_t m, const int32_t *
                        sys->tets, dt, m, cp, ri, gv);
     ZI_HIP(hipGetLastError());
     ZI_HIP(hipStreamSynchronize(s));
+    return ZI_OK;
+}
+
+zi_status zi_eit_columns_impl(const zi_system *sys, const double *U, int32_t P, int32_t ne,
+                              const int32_t *elems, int32_t *cp, int32_t *ri, double *gv,
+                              hipStream_t s) {
+    if (elems) {
+        Pool tmp;
+        int *flags = nullptr;
+        ZI_TRY(tmp.alloc(&flags, 1));
+        ZI_TRY(fill_i32(flags, 0, 1, s));
+        hipLaunchKernelGGL(k_validate_dipoles, dim3(grid_for(ne, 256)), dim3(256), 0, s, elems,
+                           ne, sys->e, flags);
+        ZI_HIP(hipGetLastError());
+        int hflags = 0;
+        ZI_TRY(read_flags(flags, s, &hflags));
+        if (hflags) {
+            set_error("element index out of range");
+            return ZI_EINVAL;
+        }
+    }
+    const size_t cols = (size_t)ne * P;
+    hipLaunchKernelGGL(k_eit_columns, dim3(grid_for(cols, 128)), dim3(128), 0, s, sys->nodes,
+                       sys->tets, elems, ne, P, U, cp, ri, gv);
+    ZI_HIP(hipGetLastError());
     return ZI_OK;
 }

@@ -210,7 +210,93 @@ __global__ __launch_bounds__(64) void k_gemm_f32(const double *W, const double *
         default: hipLaunchKernelGGL(KER<16>, __VA_ARGS__); break;      \
     }
 
+// Mi = Minv I (L x P) and y_bg = R Mi; one thread per (l, p).
+__global__ void k_minv_apply(const double *Minv, const double *I, int L, int P, double *Mi) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * P) return;
+    const int l = idx / P, p = idx % P;
+    double s = 0.0;
+    for (int k = 0; k < L; ++k) s = fma(Minv[(size_t)l * L + k], I[(size_t)k * P + p], s);
+    Mi[idx] = s;
+}
+
+__global__ void k_avg_ref(const double *Mi, int L, int P, double *y) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= L * P) return;
+    const int p = idx % P;
+    double mean = 0.0;
+    for (int k = 0; k < L; ++k) mean += Mi[(size_t)k * P + p];
+    y[idx] = Mi[idx] - mean / L;
+}
+
+// U = T Mi (n x P), one thread per (i, p).
+__global__ void k_apply_T(const double *T, const double *Mi, int32_t n, int L, int P, double *U) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * P) return;
+    const int64_t i = idx / P;
+    const int p = (int)(idx % P);
+    double s = 0.0;
+    for (int l = 0; l < L; ++l) s = fma(T[i * L + l], Mi[(size_t)l * P + p], s);
+    U[idx] = s;
+}
+
 }  // namespace
+
+zi_status zi_eit_source_impl(const zi_system *sys, const double *T, int32_t P, const double *I,
+                             int32_t ne, const int32_t *elems, int32_t *cp, int32_t *ri,
+                             double *gv, double *y_bg, hipStream_t s) {
+    const int L = sys->L;
+    if (L > 1024) {
+        set_error("zi_eit_source supports at most 1024 electrodes");
+        return ZI_EINVAL;
+    }
+    for (int p = 0; p < P; ++p) {
+        double sum = 0.0, mx = 0.0;
+        for (int l = 0; l < L; ++l) {
+            sum += I[(size_t)l * P + p];
+            mx = fmax(mx, fabs(I[(size_t)l * P + p]));
+        }
+        if (!(fabs(sum) <= 1e-12 * mx)) {
+            set_error("current pattern %d does not sum to zero", p);
+            return ZI_EINVAL;
+        }
+    }
+    Pool tmp;
+    double *S = nullptr, *Lf = nullptr, *Minv = nullptr, *W = nullptr, *Id = nullptr,
+           *Mi = nullptr, *Y = nullptr, *U = nullptr;
+    int *flag = nullptr;
+    ZI_TRY(tmp.alloc(&S, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&Lf, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&Minv, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&W, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&Id, (size_t)L * P));
+    ZI_TRY(tmp.alloc(&Mi, (size_t)L * P));
+    ZI_TRY(tmp.alloc(&Y, (size_t)L * P));
+    ZI_TRY(tmp.alloc(&U, (size_t)sys->n * P));
+    ZI_TRY(tmp.alloc(&flag, 1));
+    ZI_TRY(fill_i32(flag, 0, 1, s));
+    ZI_HIP(hipMemcpyAsync(Id, I, sizeof(double) * L * P, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_schur, dim3(L), dim3(64), 0, s, sys->e_ptr, sys->e_item, sys->b_row,
+                       sys->b_val, sys->C, T, L, S);
+    hipLaunchKernelGGL(k_chol_w, dim3(1), dim3(CHOL_THREADS), 0, s, S, L, Lf, Minv, W, flag);
+    hipLaunchKernelGGL(k_minv_apply, dim3(grid_for((size_t)L * P, 128)), dim3(128), 0, s, Minv, Id,
+                       L, P, Mi);
+    hipLaunchKernelGGL(k_avg_ref, dim3(grid_for((size_t)L * P, 128)), dim3(128), 0, s, Mi, L, P, Y);
+    hipLaunchKernelGGL(k_apply_T, dim3(grid_for((size_t)sys->n * P, 256)), dim3(256), 0, s, T, Mi,
+                       sys->n, L, P, U);
+    ZI_HIP(hipGetLastError());
+    int hflag = 0;
+    ZI_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipStreamSynchronize(s));
+    if (hflag) {
+        set_error("M = C - B^T T is not positive definite");
+        return ZI_EBREAKDOWN;
+    }
+    ZI_TRY(zi_eit_columns_impl(sys, U, P, ne, elems, cp, ri, gv, s));
+    if (y_bg) ZI_HIP(hipMemcpyAsync(y_bg, Y, sizeof(double) * L * P, hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipStreamSynchronize(s));
+    return ZI_OK;
+}
 
 zi_status zi_leadfield_impl(const zi_system *csys, const double *T, int32_t n_cols,
                             const int32_t *cp, const int32_t *ri, const double *gv, double *LF,

@@ -20,6 +20,7 @@
 // neighbours) stay in one XCD's L2.  Dot-product partials are reduced inside
 // the block in a fixed order and across blocks by the red_* kernels in a
 // fixed order, so results are bitwise reproducible.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -70,54 +71,111 @@ struct Lane {
     }
 };
 
+// Pairs of block-vector entries: double2 (FP64 mode) or float2 (the float32
+// search directions of the mixed-precision mode); arithmetic on pairs is
+// written out component-wise through d2/f2 conversions.
 __device__ __forceinline__ double2 ld2(const double *p) {
     return *reinterpret_cast<const double2 *>(p);
+}
+__device__ __forceinline__ double2 ld2(const float *p) {
+    const float2 v = *reinterpret_cast<const float2 *>(p);
+    return make_double2((double)v.x, (double)v.y);
 }
 __device__ __forceinline__ void st2(double *p, double2 v) {
     *reinterpret_cast<double2 *>(p) = v;
 }
+__device__ __forceinline__ void st2(float *p, double2 v) {
+    *reinterpret_cast<float2 *>(p) = make_float2((float)v.x, (float)v.y);
+}
+template <class T>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = double2;
+    __device__ static double2 zero() { return make_double2(0.0, 0.0); }
+    __device__ static double2 load(const double *p) { return *reinterpret_cast<const double2 *>(p); }
+    __device__ static void store(double *p, double2 v) { *reinterpret_cast<double2 *>(p) = v; }
+    __device__ static double2 widen(double2 v) { return v; }
+};
+template <>
+struct Pair<float> {
+    using type = float2;
+    __device__ static float2 zero() { return make_float2(0.f, 0.f); }
+    __device__ static float2 load(const float *p) { return *reinterpret_cast<const float2 *>(p); }
+    __device__ static void store(float *p, float2 v) { *reinterpret_cast<float2 *>(p) = v; }
+    __device__ static double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
+};
 
-// acc = sum_k a_k X[j_k, c..c+1] over row `row`, in column order.
-template <int NV>
+// Broadcast lane u of the LPR-lane row group (readlane when one row fills
+// the wave, a cross-lane permute otherwise).
+template <int LPR>
+__device__ __forceinline__ int bcast(int v, int u) {
+    if constexpr (LPR == 64)
+        return __builtin_amdgcn_readlane(v, u);
+    else
+        return __shfl(v, u, LPR);
+}
+template <int LPR>
+__device__ __forceinline__ float bcast(float v, int u) {
+    if constexpr (LPR == 64)
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), u));
+    else
+        return __shfl(v, u, LPR);
+}
+template <int LPR>
+__device__ __forceinline__ double bcast(double v, int u) {
+    if constexpr (LPR == 64) {
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), u);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), u);
+        return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+    } else {
+        return __shfl(v, u, LPR);
+    }
+}
+
+// acc = sum_k a_k X[j_k, c..c+1] over row `row`, in column order.  The row's
+// (column, value) pairs are fetched BATCH at a time with one coalesced load
+// (lane u of the group holds entry u) and broadcast, so all gathers of X for
+// the batch are in flight together.
+template <int LPR, int NV, class T>
 __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
                                             const int32_t *__restrict__ ci,
-                                            const double *__restrict__ va,
-                                            const double *__restrict__ X, int ldp, int row,
-                                            const int c[NV], const bool ok[NV], double2 acc[NV]) {
+                                            const T *__restrict__ va,
+                                            const T *__restrict__ X, int ldp, int row,
+                                            int lr, const int c[NV], const bool ok[NV],
+                                            typename Pair<T>::type acc[NV]) {
+    using PT = Pair<T>;
+    constexpr int BATCH = LPR < 8 ? LPR : 8;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = make_double2(0.0, 0.0);
+    for (int v = 0; v < NV; ++v) acc[v] = PT::zero();
     const int s = rp[row], e = rp[row + 1];
-    int k = s;
-    for (; k + 4 <= e; k += 4) {
-        int j[4];
-        double a[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            j[u] = ci[k + u];
-            a[u] = va[k + u];
+    for (int kb = s; kb < e; kb += BATCH) {
+        const int cnt = e - kb;
+        int jv = row;
+        T av = T(0);
+        if (lr < BATCH && lr < cnt) {
+            jv = ci[kb + lr];
+            av = va[kb + lr];
         }
-        double2 x[4][NV];
+        typename PT::type x[BATCH][NV];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < BATCH; ++u) {
+            const int j = bcast<LPR>(jv, u);
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                x[u][v] = ok[v] ? ld2(X + (size_t)j[u] * ldp + c[v]) : make_double2(0.0, 0.0);
+                x[u][v] = (u < cnt && ok[v]) ? PT::load(X + (size_t)j * ldp + c[v]) : PT::zero();
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < BATCH; ++u) {
+            const T a = bcast<LPR>(av, u);
+            if (u < cnt) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                acc[v].x = fma(a[u], x[u][v].x, acc[v].x);
-                acc[v].y = fma(a[u], x[u][v].y, acc[v].y);
+                for (int v = 0; v < NV; ++v) {
+                    acc[v].x = fma(a, x[u][v].x, acc[v].x);
+                    acc[v].y = fma(a, x[u][v].y, acc[v].y);
+                }
             }
-    }
-    for (; k < e; ++k) {
-        const int j = ci[k];
-        const double a = va[k];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double2 x = ok[v] ? ld2(X + (size_t)j * ldp + c[v]) : make_double2(0.0, 0.0);
-            acc[v].x = fma(a, x.x, acc[v].x);
-            acc[v].y = fma(a, x.y, acc[v].y);
         }
     }
 }
@@ -153,13 +211,14 @@ __device__ __forceinline__ void block_partials(const Geom &g, const Lane<LPR, NV
 
 // ---------------------------------------------------------------------------
 
-// Y = A X; with WITH_DOT also the partials of sum_i X[i,c] Y[i,c].
-template <int LPR, int NV, bool WITH_DOT>
+// Y = A X; with WITH_DOT also the partials of sum_i X[i,c] Y[i,c] (in FP64).
+template <int LPR, int NV, class T, bool WITH_DOT>
 __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ ci,
-                                                const double *__restrict__ va,
-                                                const double *__restrict__ X,
-                                                double *__restrict__ Y, double *part) {
+                                                const T *__restrict__ va,
+                                                const T *__restrict__ X, T *__restrict__ Y,
+                                                double *part) {
+    using PT = Pair<T>;
     int cc, rt;
     if (!block_tile(g, cc, rt)) return;
     Lane<LPR, NV> ln(g, cc);
@@ -169,16 +228,17 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
     const int r0 = rt * g.rb;
     const int r1 = min(g.n, r0 + g.rb);
     for (int row = r0 + ln.slot; row < r1; row += Lane<LPR, NV>::RSTEP) {
-        double2 acc[NV];
-        row_product<NV>(rp, ci, va, X, g.ldp, row, ln.c, ln.ok, acc);
+        typename PT::type acc[NV];
+        row_product<LPR, NV, T>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (!ln.ok[v]) continue;
-            st2(Y + (size_t)row * g.ldp + ln.c[v], acc[v]);
+            PT::store(Y + (size_t)row * g.ldp + ln.c[v], acc[v]);
             if (WITH_DOT) {
-                const double2 p = ld2(X + (size_t)row * g.ldp + ln.c[v]);
-                dotacc[0][v].x = fma(p.x, acc[v].x, dotacc[0][v].x);
-                dotacc[0][v].y = fma(p.y, acc[v].y, dotacc[0][v].y);
+                const double2 p = PT::widen(PT::load(X + (size_t)row * g.ldp + ln.c[v]));
+                const double2 q = PT::widen(acc[v]);
+                dotacc[0][v].x = fma(p.x, q.x, dotacc[0][v].x);
+                dotacc[0][v].y = fma(p.y, q.y, dotacc[0][v].y);
             }
         }
     }
@@ -188,18 +248,21 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
     }
 }
 
+constexpr int UNROLL = 4;   // rows per lane per step in the streaming kernels
+
 // X += alpha P, R -= alpha Q; partials r.D^-1 r and r.r of the new R.
-template <int LPR, int NV>
+template <int LPR, int NV, class TP>
 __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restrict__ alpha,
                                                   const double *__restrict__ dinv,
                                                   double *__restrict__ X,
                                                   double *__restrict__ R,
-                                                  const double *__restrict__ P,
-                                                  const double *__restrict__ Q, double *prz,
+                                                  const TP *__restrict__ P,
+                                                  const TP *__restrict__ Q, double *prz,
                                                   double *prr) {
     int cc, rt;
     if (!block_tile(g, cc, rt)) return;
     Lane<LPR, NV> ln(g, cc);
+    constexpr int RS = Lane<LPR, NV>::RSTEP;
     double2 acc[2][NV];
     double2 al[NV];
 #pragma unroll
@@ -209,24 +272,43 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
     }
     const int r0 = rt * g.rb;
     const int r1 = min(g.n, r0 + g.rb);
-    for (int row = r0 + ln.slot; row < r1; row += Lane<LPR, NV>::RSTEP) {
-        const double di = dinv[row];
+    for (int base = r0 + ln.slot; base < r1; base += UNROLL * RS) {
+        double2 x[UNROLL][NV], r[UNROLL][NV], p[UNROLL][NV], q[UNROLL][NV];
+        double di[UNROLL];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            if (!ln.ok[v]) continue;
-            const size_t o = (size_t)row * g.ldp + ln.c[v];
-            double2 x = ld2(X + o), r = ld2(R + o);
-            const double2 p = ld2(P + o), q = ld2(Q + o);
-            x.x = fma(al[v].x, p.x, x.x);
-            x.y = fma(al[v].y, p.y, x.y);
-            r.x = fma(-al[v].x, q.x, r.x);
-            r.y = fma(-al[v].y, q.y, r.y);
-            st2(X + o, x);
-            st2(R + o, r);
-            acc[0][v].x = fma(r.x, r.x * di, acc[0][v].x);
-            acc[0][v].y = fma(r.y, r.y * di, acc[0][v].y);
-            acc[1][v].x = fma(r.x, r.x, acc[1][v].x);
-            acc[1][v].y = fma(r.y, r.y, acc[1][v].y);
+        for (int u = 0; u < UNROLL; ++u) {
+            const int row = base + u * RS;
+            const bool rv = row < r1;
+            di[u] = rv ? dinv[row] : 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const size_t o = (size_t)row * g.ldp + ln.c[v];
+                const bool on = rv && ln.ok[v];
+                x[u][v] = on ? ld2(X + o) : make_double2(0.0, 0.0);
+                r[u][v] = on ? ld2(R + o) : make_double2(0.0, 0.0);
+                p[u][v] = on ? ld2(P + o) : make_double2(0.0, 0.0);
+                q[u][v] = on ? ld2(Q + o) : make_double2(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int row = base + u * RS;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                if (!(row < r1 && ln.ok[v])) continue;
+                const size_t o = (size_t)row * g.ldp + ln.c[v];
+                double2 xx = x[u][v], rr = r[u][v];
+                xx.x = fma(al[v].x, p[u][v].x, xx.x);
+                xx.y = fma(al[v].y, p[u][v].y, xx.y);
+                rr.x = fma(-al[v].x, q[u][v].x, rr.x);
+                rr.y = fma(-al[v].y, q[u][v].y, rr.y);
+                st2(X + o, xx);
+                st2(R + o, rr);
+                acc[0][v].x = fma(rr.x, rr.x * di[u], acc[0][v].x);
+                acc[0][v].y = fma(rr.y, rr.y * di[u], acc[0][v].y);
+                acc[1][v].x = fma(rr.x, rr.x, acc[1][v].x);
+                acc[1][v].y = fma(rr.y, rr.y, acc[1][v].y);
+            }
         }
     }
     double *const parts[2] = {prz, prr};
@@ -234,36 +316,52 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
 }
 
 // P = D^-1 R + beta P (beta == nullptr: P = D^-1 R).
-template <int LPR, int NV>
+template <int LPR, int NV, class TP>
 __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restrict__ beta,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ R,
-                                                   double *__restrict__ P) {
+                                                   TP *__restrict__ P) {
     int cc, rt;
     if (!block_tile(g, cc, rt)) return;
     Lane<LPR, NV> ln(g, cc);
+    constexpr int RS = Lane<LPR, NV>::RSTEP;
     double2 be[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
         be[v] = (ln.ok[v] && beta) ? ld2(beta + ln.c[v]) : make_double2(0.0, 0.0);
     const int r0 = rt * g.rb;
     const int r1 = min(g.n, r0 + g.rb);
-    for (int row = r0 + ln.slot; row < r1; row += Lane<LPR, NV>::RSTEP) {
-        const double di = dinv[row];
+    for (int base = r0 + ln.slot; base < r1; base += UNROLL * RS) {
+        double2 r[UNROLL][NV], p[UNROLL][NV];
+        double di[UNROLL];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            if (!ln.ok[v]) continue;
-            const size_t o = (size_t)row * g.ldp + ln.c[v];
-            const double2 r = ld2(R + o);
-            double2 p;
-            if (beta) {
-                p = ld2(P + o);
-                p.x = fma(be[v].x, p.x, r.x * di);
-                p.y = fma(be[v].y, p.y, r.y * di);
-            } else {
-                p = make_double2(r.x * di, r.y * di);
+        for (int u = 0; u < UNROLL; ++u) {
+            const int row = base + u * RS;
+            const bool rv = row < r1;
+            di[u] = rv ? dinv[row] : 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const size_t o = (size_t)row * g.ldp + ln.c[v];
+                const bool on = rv && ln.ok[v];
+                r[u][v] = on ? ld2(R + o) : make_double2(0.0, 0.0);
+                p[u][v] = (on && beta) ? ld2(P + o) : make_double2(0.0, 0.0);
             }
-            st2(P + o, p);
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int row = base + u * RS;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                if (!(row < r1 && ln.ok[v])) continue;
+                double2 pn;
+                if (beta) {
+                    pn.x = fma(be[v].x, p[u][v].x, r[u][v].x * di[u]);
+                    pn.y = fma(be[v].y, p[u][v].y, r[u][v].y * di[u]);
+                } else {
+                    pn = make_double2(r[u][v].x * di[u], r[u][v].y * di[u]);
+                }
+                st2(P + (size_t)row * g.ldp + ln.c[v], pn);
+            }
         }
     }
 }
@@ -399,6 +497,24 @@ __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, co
     }
 }
 
+// Iterative refinement: after the true residual R = B - A X (FP64) is formed,
+// columns whose true residual misses the tolerance restart with P = D^-1 R.
+__global__ __launch_bounds__(RED) void k_red_refine(Scal sc, const double *prz,
+                                                    const double *prr, int nrt, int L,
+                                                    double tol2) {
+    const int c = blockIdx.x;
+    const double rz = col_sum(prz, nrt, c);
+    const double rr = col_sum(prr, nrt, c);
+    if (threadIdx.x == 0) {
+        const int again = (c < L && sc.bb[c] > 0.0 && rr > tol2 * sc.bb[c]) ? 1 : 0;
+        sc.active[c] = again;
+        sc.rr[c] = rr;
+        if (again) sc.rho[c] = rz;
+        sc.alpha[c] = 0.0;
+        sc.beta[c] = 0.0;
+    }
+}
+
 __global__ __launch_bounds__(RED) void k_red_sum(const double *part, int nrt, double *out) {
     const int c = blockIdx.x;
     const double s = col_sum(part, nrt, c);
@@ -469,30 +585,29 @@ Geom make_geom(int n, int ldp, int tile) {
     return g;
 }
 
-template <int LPR, int NV>
-void launch_spmm(const Geom &g, hipStream_t s, const zi_system *sys, const double *X, double *Y,
-                 double *part) {
+template <int LPR, int NV, class T>
+void launch_spmm(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t *ci, const T *va,
+                 const T *X, T *Y, double *part) {
     if (part)
-        hipLaunchKernelGGL((k_spmm<LPR, NV, true>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g,
-                           sys->row_ptr, sys->col, sys->val, X, Y, part);
+        hipLaunchKernelGGL((k_spmm<LPR, NV, T, true>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, rp,
+                           ci, va, X, Y, part);
     else
-        hipLaunchKernelGGL((k_spmm<LPR, NV, false>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g,
-                           sys->row_ptr, sys->col, sys->val, X, Y, part);
+        hipLaunchKernelGGL((k_spmm<LPR, NV, T, false>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, rp,
+                           ci, va, X, Y, part);
 }
 
-template <int LPR, int NV>
+template <int LPR, int NV, class TP>
 void launch_update(const Geom &g, hipStream_t s, const double *alpha, const double *dinv,
-                   double *X, double *R, const double *P, const double *Q, double *prz,
-                   double *prr) {
-    hipLaunchKernelGGL((k_update<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, alpha, dinv, X,
-                       R, P, Q, prz, prr);
+                   double *X, double *R, const TP *P, const TP *Q, double *prz, double *prr) {
+    hipLaunchKernelGGL((k_update<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, alpha, dinv,
+                       X, R, P, Q, prz, prr);
 }
 
-template <int LPR, int NV>
+template <int LPR, int NV, class TP>
 void launch_pupdate(const Geom &g, hipStream_t s, const double *beta, const double *dinv,
-                    const double *R, double *P) {
-    hipLaunchKernelGGL((k_pupdate<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, beta, dinv, R,
-                       P);
+                    const double *R, TP *P) {
+    hipLaunchKernelGGL((k_pupdate<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, beta, dinv,
+                       R, P);
 }
 
 template <int LPR, int NV>
@@ -500,6 +615,11 @@ void launch_residual(const Geom &g, hipStream_t s, const zi_system *sys, const d
                      const double *Q, double *R, double *pbb, double *prz, double *prr) {
     hipLaunchKernelGGL((k_residual<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, sys->b_ptr,
                        sys->b_col, sys->b_val, dinv, Q, R, pbb, prz, prr);
+}
+
+__global__ void k_to_f32(const double *a, int64_t n, float *b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
 }
 
 __global__ void k_dinv(const double *d, int32_t n, double *dinv) {
@@ -589,33 +709,163 @@ struct EventTimer {
 
 }  // namespace
 
-zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_solve_stats *st,
-                        hipStream_t s) {
-    const auto t_start = std::chrono::steady_clock::now();
+namespace {
+
+// One transfer-matrix solve split into phases, so that the iteration loop can
+// be replayed as a hipGraph and several systems can share one graph.
+struct SolveCtx {
+    zi_system *sys = nullptr;
+    zi_solver_ws *ws = nullptr;
+    Geom g{};
+    int tile = 0, ldp = 0, L = 0, maxit = 0, check = 0;
+    double tol = 0, tol2 = 0;
+    bool mixed = false, timing = false;
+    Scal sc{};
+    EventTimer timer{nullptr};
+    std::vector<hipEvent_t> ev_spmm, ev_upd;
+    int it = 0;               // iterations of the block loop so far
+    int refinements = 0;
+    bool any_active = true;
+    bool done = false;        // no further iterations wanted
+    int32_t h_flag = 0;
+    std::vector<int32_t> h_active;
+    std::chrono::steady_clock::time_point t_start;
+    float *P32() const { return reinterpret_cast<float *>(ws->P); }
+    float *Q32() const { return reinterpret_cast<float *>(ws->Q); }
+};
+
+zi_status read_active(SolveCtx &c, hipStream_t s) {
+    ZI_HIP(hipMemcpyAsync(c.h_active.data(), c.sc.active, sizeof(int32_t) * c.ldp,
+                          hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(&c.h_flag, c.sc.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipStreamSynchronize(s));
+    c.any_active = false;
+    for (int k = 0; k < c.ldp; ++k) c.any_active = c.any_active || c.h_active[k];
+    return ZI_OK;
+}
+
+// Enqueue one PCG iteration (5 kernels, no host synchronisation).  TP is the
+// element type of P and of Q = A P; the matrix values have the same type.
+template <class TP>
+zi_status enqueue_iteration(SolveCtx &c, const TP *va, TP *P, TP *Q, hipStream_t s) {
+    zi_solver_ws *ws = c.ws;
+    const Geom &g = c.g;
+    const int tile = c.tile;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    if (c.timing) {
+        ZI_TRY(c.timer.get(&e0));
+        ZI_TRY(c.timer.get(&e1));
+        ZI_HIP(hipEventRecord(e0, s));
+    }
+    ZI_TILE_SWITCH(tile, launch_spmm, g, s, c.sys->sp_ptr, c.sys->sp_col, va, (const TP *)P, Q,
+                   ws->part[0]);
+    if (c.timing) ZI_HIP(hipEventRecord(e1, s));
+    hipLaunchKernelGGL(k_red_alpha, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[0], g.nrt);
+    if (c.timing) {
+        ZI_TRY(c.timer.get(&e2));
+        ZI_TRY(c.timer.get(&e3));
+        ZI_HIP(hipEventRecord(e2, s));
+    }
+    ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)c.sc.alpha, (const double *)ws->dinv,
+                   ws->X, ws->R, (const TP *)P, (const TP *)Q, ws->part[1], ws->part[2]);
+    if (c.timing) {
+        ZI_HIP(hipEventRecord(e3, s));
+        c.ev_spmm.push_back(e0);
+        c.ev_spmm.push_back(e1);
+        c.ev_upd.push_back(e2);
+        c.ev_upd.push_back(e3);
+    }
+    hipLaunchKernelGGL(k_red_beta, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[1], ws->part[2],
+                       g.nrt, c.tol2);
+    ZI_TILE_SWITCH(tile, launch_pupdate, g, s, (const double *)c.sc.beta, (const double *)ws->dinv,
+                   (const double *)ws->R, P);
+    ZI_HIP(hipGetLastError());
+    return ZI_OK;
+}
+
+zi_status enqueue_iterations(SolveCtx &c, int count, hipStream_t s) {
+    for (int k = 0; k < count; ++k) {
+        if (c.mixed) {
+            ZI_TRY(enqueue_iteration<float>(c, c.sys->sp_val32, c.P32(), c.Q32(), s));
+        } else {
+            ZI_TRY(enqueue_iteration<double>(c, c.sys->sp_val, c.ws->P, c.ws->Q, s));
+        }
+    }
+    return ZI_OK;
+}
+
+// R = B - A X in FP64 with its partials (b.b, r.D^-1 r, r.r) in part[0..2].
+zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r) {
+    zi_solver_ws *ws = c.ws;
+    ZI_TILE_SWITCH(c.tile, launch_spmm, c.g, s, c.sys->sp_ptr, c.sys->sp_col,
+                   (const double *)c.sys->sp_val, (const double *)ws->X, ws->Q, (double *)nullptr);
+    ZI_TILE_SWITCH(c.tile, launch_residual, c.g, s, c.sys, ws->dinv, ws->Q,
+                   write_r ? ws->R : (double *)nullptr, ws->part[0], ws->part[1], ws->part[2]);
+    ZI_HIP(hipGetLastError());
+    return ZI_OK;
+}
+
+zi_status enqueue_restart_direction(SolveCtx &c, hipStream_t s) {
+    if (c.mixed) {
+        ZI_TILE_SWITCH(c.tile, launch_pupdate, c.g, s, (const double *)nullptr,
+                       (const double *)c.ws->dinv, (const double *)c.ws->R, c.P32());
+    } else {
+        ZI_TILE_SWITCH(c.tile, launch_pupdate, c.g, s, (const double *)nullptr,
+                       (const double *)c.ws->dinv, (const double *)c.ws->R, c.ws->P);
+    }
+    ZI_HIP(hipGetLastError());
+    return ZI_OK;
+}
+
+int pick_tile(const zi_system *sys, int ldp, int precision, int requested) {
+    if (requested >= 0) return requested;
+    if (sys->tuned_ldp[precision] == ldp && sys->tuned_tile[precision] >= 0)
+        return sys->tuned_tile[precision];
+    return auto_tile(ldp);
+}
+
+// Validate options, prepare the workspace and enqueue the initial state:
+// X = x0 or 0, R = B - A X, the per-column scalars and P = D^-1 R.
+zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipStream_t s) {
+    c.t_start = std::chrono::steady_clock::now();
     const int n = sys->n, L = sys->L;
     const int ldp = L + (L & 1);
-    const double tol = o->tol > 0 ? o->tol : 1e-8;
-    const double tol2 = tol * tol;
-    const int maxit = o->maxit > 0 ? o->maxit : 50000;
-    const int check = o->check_every > 0 ? o->check_every : 8;
-    int tile = o->tile;
-    if (tile < 0) tile = auto_tile(ldp);
-    if (tile >= NTILES) {
-        set_error("tile %d out of range", tile);
-        return ZI_EINVAL;
-    }
     if (o->precond != ZI_PREC_JACOBI && o->precond != ZI_PREC_LDP) {
         set_error("unknown preconditioner %d", o->precond);
         return ZI_EINVAL;
     }
-    if (o->precision != ZI_FP64) {
-        set_error("precision %d not available in this build", o->precision);
+    if (o->precision != ZI_FP64 && o->precision != ZI_FP32_SPMM_IR) {
+        set_error("unknown precision %d", o->precision);
         return ZI_EINVAL;
     }
-    const Geom g = make_geom(n, ldp, tile);
+    const int tile = pick_tile(sys, ldp, o->precision, o->tile);
+    if (tile >= NTILES) {
+        set_error("tile %d out of range", tile);
+        return ZI_EINVAL;
+    }
+    c.mixed = o->precision == ZI_FP32_SPMM_IR;
     ZI_TRY(ensure_ws(sys, ldp, max_nrt(n, ldp)));
     zi_solver_ws *ws = sys->ws;
-    Scal sc;
+    if (c.mixed && !sys->sp_val32) {
+        ZI_TRY(sys->pool.alloc(&sys->sp_val32, (size_t)sys->sp_nnz));
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((sys->sp_nnz + 255) / 256)), dim3(256), 0, s,
+                           sys->sp_val, sys->sp_nnz, sys->sp_val32);
+        ZI_HIP(hipGetLastError());
+    }
+    c.sys = sys;
+    c.ws = ws;
+    c.g = make_geom(n, ldp, tile);
+    c.tile = tile;
+    c.ldp = ldp;
+    c.L = L;
+    c.maxit = o->maxit > 0 ? o->maxit : 50000;
+    c.check = o->check_every > 0 ? o->check_every : 8;
+    c.tol = o->tol > 0 ? o->tol : 1e-8;
+    c.tol2 = c.tol * c.tol;
+    c.timing = o->timing != 0 && o->graph == 0;
+    c.timer = EventTimer{&ws->ev};
+    c.h_active.assign(ldp, 0);
+    Scal &sc = c.sc;
     sc.rho = ws->sc_d;
     sc.alpha = ws->sc_d + ldp;
     sc.beta = ws->sc_d + 2 * ldp;
@@ -625,142 +875,339 @@ zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_so
     sc.active = ws->sc_i + ldp;
     sc.flag = ws->sc_i + 2 * ldp;
 
-    // preconditioner
     hipLaunchKernelGGL(k_dinv, dim3((n + 255) / 256), dim3(256), 0, s,
                        o->precond == ZI_PREC_LDP ? sys->absrow : sys->diag, n, ws->dinv);
     ZI_TRY(fill_i32(sc.flag, 0, 1, s));
-
-    // X = x0 or 0; R = B - A X
+    ZI_TRY(fill_f64(ws->X, 0.0, (size_t)n * ldp, s));
     if (o->x0) {
-        ZI_TRY(fill_f64(ws->X, 0.0, (size_t)n * ldp, s));
         ZI_TRY(copy_cols(o->x0, L, ws->X, ldp, n, L, s));
-        ZI_TILE_SWITCH(tile, launch_spmm, g, s, sys, ws->X, ws->Q, (double *)nullptr);
+        ZI_TRY(true_residual(c, s, true));
     } else {
-        ZI_TRY(fill_f64(ws->X, 0.0, (size_t)n * ldp, s));
+        ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, ws->dinv, (const double *)nullptr,
+                       ws->R, ws->part[0], ws->part[1], ws->part[2]);
     }
-    ZI_TILE_SWITCH(tile, launch_residual, g, s, sys, ws->dinv, o->x0 ? ws->Q : nullptr, ws->R,
-                   ws->part[0], ws->part[1], ws->part[2]);
     hipLaunchKernelGGL(k_red_init, dim3(ldp), dim3(RED), 0, s, sc, ws->part[0], ws->part[1],
-                       ws->part[2], g.nrt, L, tol2);
-    ZI_TILE_SWITCH(tile, launch_pupdate, g, s, (const double *)nullptr, ws->dinv, ws->R, ws->P);
+                       ws->part[2], c.g.nrt, L, c.tol2);
+    ZI_TRY(enqueue_restart_direction(c, s));
+    ZI_TRY(read_active(c, s));
+    c.done = !c.any_active;
+    return ZI_OK;
+}
+
+// After the recurrence of every column has converged: in the mixed mode run
+// one FP64 refinement step (true residual, restart of the columns that miss
+// the tolerance).  Sets c.done when nothing is left to iterate.
+zi_status solve_after_converged(SolveCtx &c, hipStream_t s) {
+    if (c.h_flag || c.it >= c.maxit || !c.mixed) {
+        c.done = true;
+        return ZI_OK;
+    }
+    ZI_TRY(true_residual(c, s, true));
+    hipLaunchKernelGGL(k_red_refine, dim3(c.ldp), dim3(RED), 0, s, c.sc, c.ws->part[1],
+                       c.ws->part[2], c.g.nrt, c.L, c.tol2);
     ZI_HIP(hipGetLastError());
-
-    EventTimer timer{&ws->ev};
-    std::vector<hipEvent_t> ev_spmm, ev_upd;
-    const bool timing = o->timing != 0;
-
-    std::vector<int32_t> h_active(ldp), h_iters(ldp);
-    int32_t h_flag = 0;
-    int it = 0;
-    bool any_active = true;
-    while (it < maxit) {
-        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
-        if (timing) {
-            ZI_TRY(timer.get(&e0));
-            ZI_TRY(timer.get(&e1));
-            ZI_HIP(hipEventRecord(e0, s));
-        }
-        ZI_TILE_SWITCH(tile, launch_spmm, g, s, sys, ws->P, ws->Q, ws->part[0]);
-        if (timing) ZI_HIP(hipEventRecord(e1, s));
-        hipLaunchKernelGGL(k_red_alpha, dim3(ldp), dim3(RED), 0, s, sc, ws->part[0], g.nrt);
-        if (timing) {
-            ZI_TRY(timer.get(&e2));
-            ZI_TRY(timer.get(&e3));
-            ZI_HIP(hipEventRecord(e2, s));
-        }
-        ZI_TILE_SWITCH(tile, launch_update, g, s, sc.alpha, ws->dinv, ws->X, ws->R, ws->P, ws->Q,
-                       ws->part[1], ws->part[2]);
-        if (timing) {
-            ZI_HIP(hipEventRecord(e3, s));
-            ev_spmm.push_back(e0);
-            ev_spmm.push_back(e1);
-            ev_upd.push_back(e2);
-            ev_upd.push_back(e3);
-        }
-        hipLaunchKernelGGL(k_red_beta, dim3(ldp), dim3(RED), 0, s, sc, ws->part[1], ws->part[2],
-                           g.nrt, tol2);
-        ZI_TILE_SWITCH(tile, launch_pupdate, g, s, sc.beta, ws->dinv, ws->R, ws->P);
-        ZI_HIP(hipGetLastError());
-        ++it;
-        if (it % check == 0 || it == maxit) {
-            ZI_HIP(hipMemcpyAsync(h_active.data(), sc.active, sizeof(int32_t) * ldp,
-                                  hipMemcpyDeviceToHost, s));
-            ZI_HIP(hipMemcpyAsync(&h_flag, sc.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            ZI_HIP(hipStreamSynchronize(s));
-            any_active = false;
-            for (int c = 0; c < ldp; ++c) any_active = any_active || h_active[c];
-            if (h_flag || !any_active) break;
-        }
+    ZI_TRY(read_active(c, s));
+    if (!c.any_active) {
+        c.done = true;
+        return ZI_OK;
     }
-    if (it == 0) {
-        ZI_HIP(hipMemcpyAsync(h_active.data(), sc.active, sizeof(int32_t) * ldp,
-                              hipMemcpyDeviceToHost, s));
-        ZI_HIP(hipStreamSynchronize(s));
-        any_active = false;
-        for (int c = 0; c < ldp; ++c) any_active = any_active || h_active[c];
-    }
+    ++c.refinements;
+    return enqueue_restart_direction(c, s);
+}
 
-    // output and statistics
+// Host check after a chunk of iterations.
+zi_status solve_check(SolveCtx &c, hipStream_t s) {
+    ZI_TRY(read_active(c, s));
+    if (c.h_flag || c.it >= c.maxit) {
+        c.done = true;
+        return ZI_OK;
+    }
+    if (!c.any_active) return solve_after_converged(c, s);
+    return ZI_OK;
+}
+
+zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
+    zi_solver_ws *ws = c.ws;
+    const int n = c.sys->n, L = c.L, ldp = c.ldp;
     ZI_TRY(copy_cols(ws->X, ldp, T, L, n, L, s));
+    std::vector<int32_t> h_iters(ldp);
     std::vector<double> h_rr(ldp), h_bb(ldp), h_true(ldp);
-    ZI_HIP(hipMemcpyAsync(h_iters.data(), sc.iters, sizeof(int32_t) * ldp, hipMemcpyDeviceToHost, s));
-    ZI_HIP(hipMemcpyAsync(h_rr.data(), sc.rr, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
-    ZI_HIP(hipMemcpyAsync(h_bb.data(), sc.bb, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(h_iters.data(), c.sc.iters, sizeof(int32_t) * ldp, hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(h_rr.data(), c.sc.rr, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(h_bb.data(), c.sc.bb, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
     if (st && st->relres_true) {
-        ZI_TILE_SWITCH(tile, launch_spmm, g, s, sys, ws->X, ws->Q, (double *)nullptr);
-        ZI_TILE_SWITCH(tile, launch_residual, g, s, sys, ws->dinv, ws->Q, (double *)nullptr,
-                       ws->part[0], ws->part[1], ws->part[2]);
-        hipLaunchKernelGGL(k_red_sum, dim3(ldp), dim3(RED), 0, s, ws->part[2], g.nrt,
-                           sc.alpha);   // alpha reused as scratch
+        ZI_TRY(true_residual(c, s, false));
+        hipLaunchKernelGGL(k_red_sum, dim3(ldp), dim3(RED), 0, s, ws->part[2], c.g.nrt,
+                           c.sc.alpha);   // alpha reused as scratch
         ZI_HIP(hipGetLastError());
-        ZI_HIP(hipMemcpyAsync(h_true.data(), sc.alpha, sizeof(double) * ldp,
+        ZI_HIP(hipMemcpyAsync(h_true.data(), c.sc.alpha, sizeof(double) * ldp,
                               hipMemcpyDeviceToHost, s));
     }
-    ZI_HIP(hipMemcpyAsync(&h_flag, sc.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t h_flag = 0;
+    ZI_HIP(hipMemcpyAsync(&h_flag, c.sc.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     ZI_HIP(hipStreamSynchronize(s));
-
     if (st) {
-        for (int c = 0; c < L; ++c) {
-            if (st->iters) st->iters[c] = h_iters[c];
-            const double bn = h_bb[c] > 0 ? h_bb[c] : 1.0;
-            if (st->relres_rec) st->relres_rec[c] = h_bb[c] > 0 ? std::sqrt(h_rr[c] / bn) : 0.0;
-            if (st->relres_true) st->relres_true[c] = h_bb[c] > 0 ? std::sqrt(h_true[c] / bn) : 0.0;
+        for (int k = 0; k < L; ++k) {
+            if (st->iters) st->iters[k] = h_iters[k];
+            const double bn = h_bb[k] > 0 ? h_bb[k] : 1.0;
+            if (st->relres_rec) st->relres_rec[k] = h_bb[k] > 0 ? std::sqrt(h_rr[k] / bn) : 0.0;
+            if (st->relres_true) st->relres_true[k] = h_bb[k] > 0 ? std::sqrt(h_true[k] / bn) : 0.0;
         }
-        st->block_iters = it;
-        st->refinements = 0;
-        st->tile = tile;
+        st->block_iters = c.it;
+        st->refinements = c.refinements;
+        st->tile = c.tile;
         st->n_kernels = 0;
-        if (timing) {
+        if (c.timing) {
             double ms_spmm = 0, ms_upd = 0;
-            for (size_t k = 0; k + 1 < ev_spmm.size(); k += 2) {
+            for (size_t k = 0; k + 1 < c.ev_spmm.size(); k += 2) {
                 float a = 0, b = 0;
-                ZI_HIP(hipEventElapsedTime(&a, ev_spmm[k], ev_spmm[k + 1]));
-                ZI_HIP(hipEventElapsedTime(&b, ev_upd[k], ev_upd[k + 1]));
+                ZI_HIP(hipEventElapsedTime(&a, c.ev_spmm[k], c.ev_spmm[k + 1]));
+                ZI_HIP(hipEventElapsedTime(&b, c.ev_upd[k], c.ev_upd[k + 1]));
                 ms_spmm += a;
                 ms_upd += b;
             }
-            const int64_t blk = (int64_t)n * ldp * 8;
-            const int64_t abytes = (int64_t)sys->nnz * 12 + (int64_t)(n + 1) * 4;
+            const int64_t pe = c.mixed ? 4 : 8;   // bytes of a P or Q entry
+            const int64_t ne = (int64_t)n * ldp;
+            const int64_t abytes = (int64_t)c.sys->sp_nnz * (4 + pe) + (int64_t)(n + 1) * 4;
             st->n_kernels = 2;
             st->kernel_name[0] = "spmm_pq";
             st->kernel_ms[0] = ms_spmm;
-            st->kernel_launches[0] = (int32_t)(ev_spmm.size() / 2);
-            st->kernel_bytes[0] = abytes + 2 * blk;            // read P, write Q
+            st->kernel_launches[0] = (int32_t)(c.ev_spmm.size() / 2);
+            st->kernel_bytes[0] = abytes + 2 * pe * ne;                 // read P, write Q
             st->kernel_name[1] = "update";
             st->kernel_ms[1] = ms_upd;
-            st->kernel_launches[1] = (int32_t)(ev_upd.size() / 2);
-            st->kernel_bytes[1] = 6 * blk + (int64_t)n * 8;    // r/w X, R; read P, Q; dinv
+            st->kernel_launches[1] = (int32_t)(c.ev_upd.size() / 2);
+            st->kernel_bytes[1] = (32 + 2 * pe) * ne + (int64_t)n * 8;  // r/w X, R; P, Q; D^-1
         }
-        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - c.t_start).count();
     }
     if (h_flag) {
         set_error("PCG breakdown: p^T A p <= 0 (matrix not positive definite)");
         return ZI_EBREAKDOWN;
     }
-    if (any_active) {
-        set_error("PCG did not reach tol %.3g within %d iterations", tol, maxit);
+    if (c.any_active) {
+        set_error("PCG did not reach tol %.3g within %d iterations", c.tol, c.maxit);
         return ZI_ENOTCONV;
     }
+    return ZI_OK;
+}
+
+// Capture `count` iterations of every listed solve into one graph: one
+// branch per solve (its own stream), forked from and joined back to the
+// internal capture stream `origin` (never the caller's stream, which may be
+// the null stream).  The graph is launched on the caller's stream.
+zi_status capture_graph(std::vector<SolveCtx *> &cs, std::vector<hipStream_t> &streams,
+                        int count, hipStream_t origin, hipGraphExec_t *exec) {
+    hipEvent_t fork, join_ev;
+    ZI_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    std::vector<hipEvent_t> joins(cs.size());
+    for (auto &e : joins) ZI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipGraph_t graph;
+    ZI_HIP(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+    zi_status st = ZI_OK;
+    if (hipEventRecord(fork, origin) != hipSuccess) st = ZI_EDEVICE;
+    for (size_t k = 0; k < cs.size() && st == ZI_OK; ++k) {
+        if (hipStreamWaitEvent(streams[k], fork, 0) != hipSuccess) {
+            st = ZI_EDEVICE;
+            break;
+        }
+        st = enqueue_iterations(*cs[k], count, streams[k]);
+        if (st == ZI_OK && hipEventRecord(joins[k], streams[k]) != hipSuccess) st = ZI_EDEVICE;
+        if (st == ZI_OK && hipStreamWaitEvent(origin, joins[k], 0) != hipSuccess) st = ZI_EDEVICE;
+    }
+    hipError_t ee = hipStreamEndCapture(origin, &graph);
+    (void)join_ev;
+    if (st == ZI_OK && ee != hipSuccess) {
+        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+        st = ZI_EDEVICE;
+    }
+    if (st == ZI_OK) {
+        hipError_t ie = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+            st = ZI_EDEVICE;
+        }
+    }
+    if (ee == hipSuccess) (void)hipGraphDestroy(graph);
+    (void)hipEventDestroy(fork);
+    for (auto &e : joins) (void)hipEventDestroy(e);
+    if (st == ZI_EDEVICE && zi::g_err_empty()) set_error("graph capture failed");
+    return st;
+}
+
+}  // namespace
+
+zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_solve_stats *st,
+                        hipStream_t s) {
+    SolveCtx c;
+    ZI_TRY(solve_begin(sys, o, c, s));
+    if (o->graph) {
+        std::vector<SolveCtx *> cs{&c};
+        hipStream_t side, cap;
+        ZI_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        ZI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        std::vector<hipStream_t> streams{side};
+        hipGraphExec_t exec = nullptr;
+        int exec_chunk = 0;
+        zi_status r = ZI_OK;
+        while (!c.done && r == ZI_OK) {
+            const int chunk = std::min(c.check, c.maxit - c.it);
+            if (!exec || chunk != exec_chunk) {
+                if (exec) (void)hipGraphExecDestroy(exec);
+                exec = nullptr;
+                r = capture_graph(cs, streams, chunk, cap, &exec);
+                if (r != ZI_OK) break;
+                exec_chunk = chunk;
+            }
+            if (hipGraphLaunch(exec, s) != hipSuccess) {
+                set_error("hipGraphLaunch failed");
+                r = ZI_EDEVICE;
+                break;
+            }
+            c.it += chunk;
+            r = solve_check(c, s);
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        (void)hipStreamDestroy(side);
+        (void)hipStreamDestroy(cap);
+        ZI_TRY(r);
+    } else {
+        while (!c.done) {
+            ZI_TRY(enqueue_iterations(c, 1, s));
+            ++c.it;
+            if (c.it % c.check == 0 || c.it >= c.maxit) ZI_TRY(solve_check(c, s));
+        }
+    }
+    return solve_end(c, T, st, s);
+}
+
+zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_solve_opts *o,
+                              double *const *T, zi_solve_stats *st, hipStream_t s) {
+    std::vector<SolveCtx> cs(nsys);
+    for (int k = 0; k < nsys; ++k) {
+        ZI_TRY(solve_begin(systems[k], o, cs[k], s));
+        cs[k].timing = false;   // events cannot be captured
+    }
+    std::vector<hipStream_t> streams(nsys + 1);   // one per system + capture origin
+    for (auto &x : streams) ZI_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    hipStream_t cap = streams[nsys];
+    struct StreamGuard {
+        std::vector<hipStream_t> &v;
+        ~StreamGuard() {
+            for (auto x : v) (void)hipStreamDestroy(x);
+        }
+    } guard{streams};
+    const int chunk = o->check_every > 0 ? o->check_every : 8;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> members, last;
+    zi_status r = ZI_OK;
+    for (;;) {
+        members.clear();
+        for (int k = 0; k < nsys; ++k)
+            if (!cs[k].done && cs[k].maxit - cs[k].it >= chunk) members.push_back(k);
+        // solves within one chunk of maxit finish on their own (no graph)
+        for (int k = 0; k < nsys && r == ZI_OK; ++k) {
+            if (cs[k].done || cs[k].maxit - cs[k].it >= chunk) continue;
+            while (!cs[k].done && r == ZI_OK) {
+                r = enqueue_iterations(cs[k], 1, s);
+                ++cs[k].it;
+                if (r == ZI_OK && cs[k].it >= cs[k].maxit) r = solve_check(cs[k], s);
+            }
+        }
+        if (r != ZI_OK || members.empty()) break;
+        if (members != last) {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+            std::vector<SolveCtx *> sel;
+            std::vector<hipStream_t> ss;
+            for (int k : members) {
+                sel.push_back(&cs[k]);
+                ss.push_back(streams[k]);
+            }
+            r = capture_graph(sel, ss, chunk, cap, &exec);
+            if (r != ZI_OK) break;
+            last = members;
+        }
+        if (hipGraphLaunch(exec, s) != hipSuccess) {
+            set_error("hipGraphLaunch failed");
+            r = ZI_EDEVICE;
+            break;
+        }
+        for (int k : members) {
+            cs[k].it += chunk;
+            r = solve_check(cs[k], s);
+            if (r != ZI_OK) break;
+        }
+        if (r != ZI_OK) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    ZI_TRY(r);
+    zi_status worst = ZI_OK;
+    for (int k = 0; k < nsys; ++k) {
+        const zi_status e = solve_end(cs[k], T[k], st ? &st[k] : nullptr, s);
+        if (e != ZI_OK && worst == ZI_OK) worst = e;
+    }
+    return worst;
+}
+
+zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, double *ms_out,
+                           hipStream_t s) {
+    const int n = sys->n, L = sys->L, ldp = L + (L & 1);
+    if (precision != ZI_FP64 && precision != ZI_FP32_SPMM_IR) {
+        set_error("unknown precision %d", precision);
+        return ZI_EINVAL;
+    }
+    ZI_TRY(ensure_ws(sys, ldp, max_nrt(n, ldp)));
+    zi_solver_ws *ws = sys->ws;
+    if (precision == ZI_FP32_SPMM_IR && !sys->sp_val32) {
+        ZI_TRY(sys->pool.alloc(&sys->sp_val32, (size_t)sys->sp_nnz));
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((sys->sp_nnz + 255) / 256)), dim3(256), 0, s,
+                           sys->sp_val, sys->sp_nnz, sys->sp_val32);
+    }
+    // a smooth, non-zero block to multiply (the solver's R buffer)
+    ZI_TRY(fill_f64(ws->R, 1.0, (size_t)n * ldp, s));
+    if (precision == ZI_FP32_SPMM_IR)
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)(((size_t)n * ldp + 255) / 256)), dim3(256), 0,
+                           s, ws->R, (int64_t)n * ldp, reinterpret_cast<float *>(ws->P));
+    else
+        ZI_HIP(hipMemcpyAsync(ws->P, ws->R, sizeof(double) * n * ldp, hipMemcpyDeviceToDevice, s));
+    ZI_HIP(hipGetLastError());
+    hipEvent_t e0, e1;
+    ZI_HIP(hipEventCreate(&e0));
+    ZI_HIP(hipEventCreate(&e1));
+    int bt = 0;
+    double bms = 1e30;
+    for (int t = 0; t < NTILES; ++t) {
+        const Geom g = make_geom(n, ldp, t);
+        double tmin = 1e30;
+        for (int rep = 0; rep < 4; ++rep) {
+            ZI_HIP(hipEventRecord(e0, s));
+            if (precision == ZI_FP32_SPMM_IR) {
+                ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
+                               (const float *)sys->sp_val32, (const float *)ws->P,
+                               reinterpret_cast<float *>(ws->Q), ws->part[0]);
+            } else {
+                ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
+                               (const double *)sys->sp_val, (const double *)ws->P, ws->Q,
+                               ws->part[0]);
+            }
+            ZI_HIP(hipEventRecord(e1, s));
+            ZI_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            ZI_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) tmin = std::min(tmin, (double)ms);   // first run warms up
+        }
+        if (ms_out) ms_out[t] = tmin;
+        if (tmin < bms) {
+            bms = tmin;
+            bt = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    sys->tuned_tile[precision] = bt;
+    sys->tuned_ldp[precision] = ldp;
+    if (best) *best = bt;
     return ZI_OK;
 }
 
@@ -780,7 +1227,8 @@ zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double 
     ZI_HIP(hipEventCreate(&e0));
     ZI_HIP(hipEventCreate(&e1));
     ZI_HIP(hipEventRecord(e0, s));
-    ZI_TILE_SWITCH(tile, launch_spmm, g, s, sys, X, Y, (double *)nullptr);
+    ZI_TILE_SWITCH(tile, launch_spmm, g, s, sys->sp_ptr, sys->sp_col, (const double *)sys->sp_val,
+                   X, Y, (double *)nullptr);
     ZI_HIP(hipGetLastError());
     ZI_HIP(hipEventRecord(e1, s));
     ZI_HIP(hipEventSynchronize(e1));

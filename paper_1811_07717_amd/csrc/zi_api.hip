@@ -9,6 +9,7 @@ namespace zi {
 namespace {
 thread_local char g_err[512] = "";
 }
+bool g_err_empty() { return g_err[0] == 0; }
 void set_error(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -96,6 +97,43 @@ zi_status zi_transfer_solve(zi_system *sys, const zi_solve_opts *opts, double *T
     ZI_GUARD(return zi_solve_impl(sys, opts, T, stats, (hipStream_t)hip_stream);)
 }
 
+zi_status zi_transfer_solve_batch(zi_system *const *systems, int32_t n_systems,
+                                  const zi_solve_opts *opts, double *const *T,
+                                  zi_solve_stats *stats, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!systems || !opts || !T || n_systems < 1) {
+        set_error("null argument or n_systems < 1");
+        return ZI_EINVAL;
+    }
+    for (int k = 0; k < n_systems; ++k) {
+        if (!systems[k] || !T[k]) {
+            set_error("null system or output %d", k);
+            return ZI_EINVAL;
+        }
+        for (int j = 0; j < k; ++j)
+            if (systems[j] == systems[k]) {
+                set_error("system %d appears twice", k);
+                return ZI_EINVAL;
+            }
+    }
+    if (opts->tol < 0 || opts->maxit < 0 || opts->x0) {
+        set_error("tol and maxit must be non-negative; x0 is not supported in batches");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_solve_batch_impl(systems, n_systems, opts, T, stats,
+                                        (hipStream_t)hip_stream);)
+}
+
+zi_status zi_autotune(zi_system *sys, int32_t precision, int32_t *best_tile, double *ms,
+                      void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!sys) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_autotune_impl(sys, precision, best_tile, ms, (hipStream_t)hip_stream);)
+}
+
 zi_status zi_leadfield(const zi_system *sys, const double *T, int32_t n_cols,
                        const int32_t *g_colptr, const int32_t *g_rowind, const double *g_val,
                        double *LF, int32_t precision, void *hip_stream) {
@@ -134,6 +172,27 @@ zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y, i
     ZI_GUARD(return zi_spmm_impl(sys, k, X, Y, tile, ms_out, (hipStream_t)hip_stream);)
 }
 
+zi_status zi_eit_source(const zi_system *sys, const double *T, int32_t n_patterns,
+                        const double *I, int32_t n_elems, const int32_t *elems,
+                        int32_t *g_colptr, int32_t *g_rowind, double *g_val, double *y_bg,
+                        void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!sys || !T || !I || !g_colptr || !g_rowind || !g_val || n_patterns < 1 || n_elems < 1) {
+        set_error("null argument, n_patterns < 1 or n_elems < 1");
+        return ZI_EINVAL;
+    }
+    if (!elems && n_elems != sys->e) {
+        set_error("elems == NULL needs n_elems == n_tets");
+        return ZI_EINVAL;
+    }
+    if ((int64_t)n_patterns * n_elems * 4 >= (int64_t)1 << 31) {
+        set_error("too many EIT source columns");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_eit_source_impl(sys, T, n_patterns, I, n_elems, elems, g_colptr, g_rowind,
+                                       g_val, y_bg, (hipStream_t)hip_stream);)
+}
+
 int32_t zi_tile_count(void) { return zi_tile_count_impl(); }
 const char *zi_tile_name(int32_t t) { return zi_tile_name_impl(t); }
 
@@ -148,6 +207,7 @@ zi_status zi_get_info(const zi_system *sys, zi_system_info *info) {
     info->ground_node = sys->ground;
     info->nnz = sys->nnz;
     info->b_nnz = sys->b_nnz;
+    info->nnz_solver = sys->sp_nnz;
     return ZI_OK;
 }
 

@@ -12,6 +12,7 @@
 namespace zi {
 
 void set_error(const char *fmt, ...);
+bool g_err_empty();
 
 #define ZI_HIP(call)                                                              \
     do {                                                                          \
@@ -114,6 +115,12 @@ struct zi_system {
     // A: mesh-graph CSR, grounded values
     int32_t *row_ptr = nullptr, *col = nullptr;
     double *val = nullptr;
+    // the solver's copy of A: off-diagonal entries below 64 eps sqrt(a_ii a_jj)
+    // (rounding residue of couplings that vanish in exact arithmetic) left out
+    int32_t *sp_ptr = nullptr, *sp_col = nullptr;
+    double *sp_val = nullptr;
+    float *sp_val32 = nullptr;   // float32 copy for the mixed-precision solve
+    int64_t sp_nnz = 0;
     double *diag = nullptr;      // a_ii
     double *absrow = nullptr;    // sum_j |a_ij|
 
@@ -129,6 +136,10 @@ struct zi_system {
     double *Pt = nullptr;        // n_cols x L (grows)
     size_t Pt_cap = 0;
 
+    // SpMM tile chosen by zi_autotune per precision (for that ldp)
+    int32_t tuned_tile[2] = {-1, -1};
+    int32_t tuned_ldp[2] = {0, 0};
+
     zi::Pool pool;               // owns every array above
     zi_solver_ws *ws = nullptr;  // lazily created
 };
@@ -138,6 +149,10 @@ zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t
                            hipStream_t s, zi_system **out);
 zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *opts, double *T,
                         zi_solve_stats *stats, hipStream_t s);
+zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_solve_opts *o,
+                              double *const *T, zi_solve_stats *st, hipStream_t s);
+zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, double *ms_out,
+                           hipStream_t s);
 zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double *Y,
                        int32_t tile, double *ms, hipStream_t s);
 zi_status zi_leadfield_impl(const zi_system *sys, const double *T, int32_t n_cols,
@@ -145,6 +160,12 @@ zi_status zi_leadfield_impl(const zi_system *sys, const double *T, int32_t n_col
                             double *LF, int32_t precision, hipStream_t s);
 zi_status zi_point_dipoles_impl(const zi_system *sys, int32_t m, const int32_t *dt,
                                 int32_t *cp, int32_t *ri, double *gv, hipStream_t s);
+zi_status zi_eit_columns_impl(const zi_system *sys, const double *U, int32_t P, int32_t ne,
+                              const int32_t *elems, int32_t *cp, int32_t *ri, double *gv,
+                              hipStream_t s);
+zi_status zi_eit_source_impl(const zi_system *sys, const double *T, int32_t P, const double *I,
+                             int32_t ne, const int32_t *elems, int32_t *cp, int32_t *ri,
+                             double *gv, double *y_bg, hipStream_t s);
 void zi_solver_ws_destroy(zi_solver_ws *ws);
 int32_t zi_tile_count_impl();
 const char *zi_tile_name_impl(int32_t t);

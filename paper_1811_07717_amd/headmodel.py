@@ -288,3 +288,18 @@ WORKLOADS = {
 
 def workload(name):
     return make_head(**WORKLOADS[name])
+
+
+def batch_heads(count=64, seed=1815, h_range=(2.5, 6.0), Ls=(32, 64, 96, 128), m=1000):
+    """Uneven head models for batched solves: per head a common radius scale
+    ~U[0.9, 1.1], each layer conductivity times exp(U[ln 0.5, ln 2]), grid
+    spacing ~U[h_range] mm and L drawn from Ls."""
+    rng = np.random.default_rng(seed)
+    heads = []
+    for k in range(count):
+        scale = rng.uniform(0.9, 1.1)
+        sig = tuple(float(s * np.exp(rng.uniform(np.log(0.5), np.log(2.0)))) for s in SIGMAS)
+        h = float(rng.uniform(*h_range))
+        L = int(rng.choice(Ls))
+        heads.append(make_head(h, L=L, m=m, seed=seed + 1 + k, sigmas=sig, scale=scale))
+    return heads

@@ -41,7 +41,7 @@ class ZiSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("x0", ctypes.c_void_p)]
+                ("tile", ctypes.c_int32), ("graph", ctypes.c_int32), ("x0", ctypes.c_void_p)]
 
 
 class ZiSolveStats(ctypes.Structure):
@@ -56,7 +56,8 @@ class ZiSolveStats(ctypes.Structure):
 class ZiInfo(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int32), ("n_tets", ctypes.c_int32),
                 ("n_electrodes", ctypes.c_int32), ("ground_node", ctypes.c_int32),
-                ("nnz", ctypes.c_int64), ("b_nnz", ctypes.c_int32)]
+                ("nnz", ctypes.c_int64), ("b_nnz", ctypes.c_int32),
+                ("nnz_solver", ctypes.c_int64)]
 
 
 class ZiView(ctypes.Structure):
@@ -73,12 +74,21 @@ SIGNATURES = [
     ("zi_transfer_solve", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ZiSolveOpts),
                                          ctypes.c_void_p, ctypes.POINTER(ZiSolveStats),
                                          ctypes.c_void_p]),
+    ("zi_transfer_solve_batch", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                               ctypes.POINTER(ZiSolveOpts),
+                                               ctypes.POINTER(ctypes.c_void_p),
+                                               ctypes.POINTER(ZiSolveStats), ctypes.c_void_p]),
+    ("zi_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, c_i32p, c_f64p,
+                                   ctypes.c_void_p]),
     ("zi_leadfield", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     ("zi_point_dipoles", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    ("zi_eit_source", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, c_f64p,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, c_f64p, ctypes.c_void_p]),
     ("zi_spmm", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_int32, c_f64p, ctypes.c_void_p]),
     ("zi_tile_count", ctypes.c_int32, []),
@@ -169,6 +179,7 @@ class System:
         _check(lib().zi_get_info(self._h, ctypes.byref(inf)), "zi_get_info")
         self.n, self.e, self.L = inf.n_nodes, inf.n_tets, inf.n_electrodes
         self.ground, self.nnz, self.b_nnz = inf.ground_node, inf.nnz, inf.b_nnz
+        self.nnz_solver = inf.nnz_solver
 
     @classmethod
     def from_head(cls, H, device="cuda", ground=-1):
@@ -218,7 +229,7 @@ class System:
     # -- solve ---------------------------------------------------------------
     def transfer_solve(self, tol=1e-8, maxit=0, precond="jacobi", precision="fp64",
                        check_every=0, timing=False, tile=-1, x0=None, out=None,
-                       raise_on_error=True):
+                       raise_on_error=True, graph=False):
         import torch
         T = out if out is not None else torch.empty((self.n, self.L), dtype=torch.float64,
                                                      device="cuda")
@@ -230,7 +241,7 @@ class System:
         st.relres_rec = rec.ctypes.data_as(c_f64p)
         st.relres_true = true.ctypes.data_as(c_f64p)
         o = ZiSolveOpts(float(tol), int(maxit), PRECOND[precond], PRECISION[precision],
-                        int(check_every), int(bool(timing)), int(tile),
+                        int(check_every), int(bool(timing)), int(tile), int(bool(graph)),
                         _dev(x0, torch.float64, "x0") if x0 is not None else None)
         rc = lib().zi_transfer_solve(self._h, ctypes.byref(o), _dev(T, torch.float64, "T"),
                                      ctypes.byref(st), _stream())
@@ -243,6 +254,15 @@ class System:
         if raise_on_error:
             _check(rc, "zi_transfer_solve")
         return T, stats
+
+    def autotune(self, precision="fp64"):
+        """Time every SpMM tile on this system; later solves use the fastest."""
+        n = lib().zi_tile_count()
+        ms = np.zeros(n)
+        best = ctypes.c_int32(-1)
+        _check(lib().zi_autotune(self._h, PRECISION[precision], ctypes.byref(best),
+                                 ms.ctypes.data_as(c_f64p), _stream()), "zi_autotune")
+        return best.value, ms
 
     def point_dipoles(self, dipole_tets):
         import torch
@@ -271,6 +291,26 @@ class System:
                "zi_leadfield")
         return LF
 
+    def eit_source(self, T, I, elems=None):
+        """Source matrix of the linearized EIT lead field and y_bg = R M^-1 I.
+
+        I: (L, P) currents (host array), elems: int32 device tensor or None."""
+        import torch
+        Ih = np.ascontiguousarray(np.asarray(I, dtype=np.float64).reshape(self.L, -1))
+        P = Ih.shape[1]
+        ne = self.e if elems is None else int(elems.shape[0])
+        cp = torch.empty(P * ne + 1, dtype=torch.int32, device="cuda")
+        ri = torch.empty(4 * P * ne, dtype=torch.int32, device="cuda")
+        gv = torch.empty(4 * P * ne, dtype=torch.float64, device="cuda")
+        ybg = np.zeros((self.L, P))
+        _check(lib().zi_eit_source(self._h, _dev(T, torch.float64, "T"), P,
+                                   Ih.ctypes.data_as(c_f64p), ne,
+                                   _dev(elems, torch.int32, "elems") if elems is not None else None,
+                                   _dev(cp, torch.int32, "colptr"), _dev(ri, torch.int32, "rowind"),
+                                   _dev(gv, torch.float64, "val"), ybg.ctypes.data_as(c_f64p),
+                                   _stream()), "zi_eit_source")
+        return (cp, ri, gv), ybg
+
     def spmm(self, X, tile=-1, out=None):
         import torch
         k = int(X.shape[1])
@@ -283,3 +323,32 @@ class System:
 
 def tile_names():
     return [lib().zi_tile_name(t).decode() for t in range(lib().zi_tile_count())]
+
+
+def transfer_solve_batch(systems, tol=1e-8, maxit=0, precond="jacobi", precision="fp64",
+                         check_every=0, tile=-1, raise_on_error=True):
+    """zi_transfer_solve_batch over a list of System objects (one hipGraph)."""
+    import torch
+    k = len(systems)
+    Ts = [torch.empty((s.n, s.L), dtype=torch.float64, device="cuda") for s in systems]
+    hs = (ctypes.c_void_p * k)(*[s._h.value for s in systems])
+    tp = (ctypes.c_void_p * k)(*[t.data_ptr() for t in Ts])
+    sts = (ZiSolveStats * k)()
+    keep = []
+    for j, s in enumerate(systems):
+        it = np.zeros(s.L, dtype=np.int32)
+        rec = np.zeros(s.L)
+        tr = np.zeros(s.L)
+        keep.append((it, rec, tr))
+        sts[j].iters = it.ctypes.data_as(c_i32p)
+        sts[j].relres_rec = rec.ctypes.data_as(c_f64p)
+        sts[j].relres_true = tr.ctypes.data_as(c_f64p)
+    o = ZiSolveOpts(float(tol), int(maxit), PRECOND[precond], PRECISION[precision],
+                    int(check_every), 0, int(tile), 1, None)
+    rc = lib().zi_transfer_solve_batch(hs, k, ctypes.byref(o), tp, sts, _stream())
+    if raise_on_error:
+        _check(rc, "zi_transfer_solve_batch")
+    stats = [dict(iters=it, relres_rec=rec, relres_true=tr, block_iters=sts[j].block_iters,
+                  refinements=sts[j].refinements, tile=sts[j].tile, seconds=sts[j].seconds)
+             for j, (it, rec, tr) in enumerate(keep)]
+    return Ts, stats, rc

@@ -97,3 +97,26 @@ def test_leadfield_properties(full):
     assert torch.isfinite(LF).all()
     cs = LF.sum(dim=0).abs().max().item()
     assert cs <= 1e-9 * LF.abs().max().item()
+
+
+def test_mixed_precision_full_size(full):
+    # The same workload with FP32 products and FP64 refinement: true residual
+    # against the oracle's A and the sampled lead-field columns, per electrode.
+    H, g, gold = full["H"], full["g"], full["gold"]
+    say("[gpu] mixed-precision solve 2 mm")
+    T, st = g.transfer_solve(tol=1e-8, precision="fp32_spmm_ir")
+    say(f"[2mm] mixed: iterations {st['iters'].min()}..{st['iters'].max()}, "
+        f"refinements {st['refinements']}, {st['seconds']:.2f} s")
+    S = fem.assemble(H.nodes, H.tets, H.sigma, H.tris, H.tri_electrode, H.Z)
+    Tn = T.cpu().numpy()
+    Bd = S["B"].toarray()
+    res = np.linalg.norm(Bd - S["A"] @ Tn, axis=0) / np.linalg.norm(Bd, axis=0)
+    assert res.max() <= 1.5e-8
+    d64 = np.linalg.norm(Tn - full["T"].cpu().numpy(), axis=0) / np.linalg.norm(Tn, axis=0)
+    say(f"[2mm] mixed vs FP64 transfer columns: max relative difference {d64.max():.2e}")
+    G = g.point_dipoles(torch.from_numpy(H.dipole_tets).cuda())
+    LF = g.leadfield(T, G).cpu().numpy()
+    got = LF[:, gold["lf_columns"]]
+    ref = np.array(gold["lf_values"]).T
+    assert lf.rdm(got, ref).max() <= 1e-4
+    assert np.abs(lf.mag(got, ref) - 1).max() <= 1e-4

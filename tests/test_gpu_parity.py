@@ -193,3 +193,26 @@ def test_leadfield_fp32_matrix_cores(case):
     m = np.abs(lf.mag(LF, ref) - 1)
     say(f"[{case['name']}] fp32 LF: RDM max {r.max():.3e}, |MAG-1| max {m.max():.3e}")
     assert r.max() <= 1e-4 and m.max() <= 1e-4
+
+
+def test_mixed_precision_refinement(case):
+    # FP32 matrix products inside FP64 recurrences, FP64 iterative refinement:
+    # the true FP64 residual must still reach the tolerance, and the lead field
+    # must match the oracle to the same bar as the FP64 solve.
+    g, S, H = case["sys"], case["S"], case["H"]
+    say(f"[gpu] mixed-precision solve {case['name']}")
+    T, st = g.transfer_solve(tol=1e-8, precision="fp32_spmm_ir")
+    Tn = T.cpu().numpy()
+    Bd = S["B"].toarray()
+    res = np.linalg.norm(Bd - S["A"] @ Tn, axis=0) / np.linalg.norm(Bd, axis=0)
+    colerr = np.linalg.norm(Tn - case["Tref"], axis=0) / np.linalg.norm(case["Tref"], axis=0)
+    say(f"[{case['name']}] mixed: iters {st['iters'].min()}..{st['iters'].max()}, "
+        f"refinements {st['refinements']}, true residual max {res.max():.2e}, "
+        f"T column error max {colerr.max():.2e}")
+    assert res.max() <= 1.5e-8
+    assert colerr.max() <= 1e-5
+    G = g.point_dipoles(torch.from_numpy(H.dipole_tets).cuda())
+    LF = g.leadfield(T, G).cpu().numpy()
+    r = lf.rdm(LF, case["LFref"])
+    m = np.abs(lf.mag(LF, case["LFref"]) - 1)
+    assert r.max() <= 1e-4 and m.max() <= 1e-4
