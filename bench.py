@@ -42,6 +42,8 @@ def parse():
                    help="also time zi_spmm with every tile on an n x L block")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="also run one torch copy of this many MiB (counter calibration)")
+    p.add_argument("--autotune", action="store_true",
+                   help="run zi_autotune on the workload before timing")
     return p.parse_args()
 
 
@@ -65,6 +67,16 @@ def traffic_for(kernel, workload):
     if not e or e.get("source_hash") != source_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def copy_bandwidth(torch, dev, mib=2048):
+    """Achievable HBM bandwidth of the library's plain 16-byte streaming copy
+    (read + write bytes / s, best of 5)."""
+    from paper_1811_07717_amd import zi
+    x = torch.ones((mib << 20) // 8, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    ms = min(zi.copy_probe(x, y) for _ in range(6))
+    return 2 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(H, L):
@@ -112,6 +124,13 @@ def main():
     LF = torch.empty((L, 3 * H.m), dtype=torch.float64, device=dev)
     s0 = zi.System(nodes, tets, sigma, tris, tre, H.Z)
     G = s0.point_dipoles(dip)
+    tuned = None
+    if a.autotune:
+        best, ms = s0.autotune(a.precision)
+        tuned = {"tile": zi.tile_names()[best], "ms": {n: float(v) for n, v in
+                                                      zip(zi.tile_names(), ms)}}
+        if a.tile < 0:
+            a.tile = best
     s0.close()
     torch.cuda.synchronize()
 
@@ -132,9 +151,9 @@ def main():
     dt = (time.perf_counter() - t0) / a.steps
 
     if a.calib_copy_mb:
-        x = torch.empty(a.calib_copy_mb << 20, dtype=torch.uint8, device=dev)
+        x = torch.ones((a.calib_copy_mb << 20) // 8, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
-        y.copy_(x)
+        zi.copy_probe(x, y)
         torch.cuda.synchronize()
 
     tiles = None
@@ -189,8 +208,11 @@ def main():
                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                      "traffic": traffic_for(dom, a.workload)},
     }
+    out["hbm_copy_gbs"] = copy_bandwidth(torch, dev)
     if tiles:
         out["spmm_tiles"] = tiles
+    if tuned:
+        out["autotune"] = tuned
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(H, L)
     print(json.dumps(out))

@@ -103,6 +103,10 @@ typedef struct {
     int32_t graph;       /* 1: replay the iteration loop as a hipGraph of
                             check_every iterations (no per-kernel timing) */
     const double *x0;    /* n_nodes x L initial iterate, or NULL for zero */
+    const int32_t *columns; /* HOST, optional: solve only these electrode
+                               columns (distinct, in [0, L)); T, x0 and the
+                               statistics then have n_columns columns */
+    int32_t n_columns;
 } zi_solve_opts;
 
 /* Statistics of zi_transfer_solve.  The HOST arrays are caller-owned, length
@@ -135,9 +139,10 @@ typedef struct {
 zi_status zi_assemble(const zi_mesh *mesh, const zi_electrodes *el,
                       int32_t ground_node, void *hip_stream, zi_system **out);
 
-/* T = A^-1 B (App. A.4): PCG of Sec. 2.3.1 on every electrode column, from
- * x0 (or 0) until ||r||_2 <= tol ||b||_2 per column.
- *   T      n_nodes x n_electrodes float64, written on ZI_OK and ZI_ENOTCONV
+/* T = A^-1 B (App. A.4): PCG of Sec. 2.3.1 on every electrode column (or the
+ * opts->columns subset), from x0 (or 0) until ||r||_2 <= tol ||b||_2 per
+ * column.
+ *   T      n_nodes x n_electrodes (or n_columns) float64, written on ZI_OK and ZI_ENOTCONV
  *          (then it holds the last iterate).
  *   stats  may be NULL.
  * ZI_ENOTCONV if a column misses the tolerance within maxit iterations;
@@ -218,6 +223,41 @@ zi_status zi_eit_source(const zi_system *sys, const double *T, int32_t n_pattern
  * event-timed kernel duration. */
 zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y,
                   int32_t tile, double *ms_out, void *hip_stream);
+
+/* ---- Learned PCG initial iterates: a mesh-graph network ------------------
+ * A K-layer network on the mesh graph of an assembled system (its CSR
+ * structure), with the symmetric normalised aggregation
+ * Ahat = D^-1/2 Adj D^-1/2.  Layer k maps H_k (n x dims[k]) to
+ * relu(H_k Ws_k + (Ahat H_k) Wn_k + b_k) (no relu on the last layer); the
+ * prediction is column 0 of H_K.  float32 throughout; weight gradients are
+ * reduced in float64 in a fixed order.  The network only proposes x0 for
+ * zi_transfer_solve; the PCG always finishes to its tolerance.
+ * Parameter layout (flat float32): for k = 0..K-1, Ws_k (dims[k] x
+ * dims[k+1], row-major), Wn_k (same), b_k (dims[k+1]).  dims[k] for k < K
+ * must be even and <= 64; dims[K] <= 64. */
+typedef struct zi_gnn zi_gnn;
+zi_status zi_gnn_create(const zi_system *sys, int32_t n_layers, const int32_t *dims /* HOST */,
+                        zi_gnn **out);
+int64_t zi_gnn_param_count(const zi_gnn *net);
+/* Parameters from / to HOST memory (setting resets the Adam moments). */
+zi_status zi_gnn_set_params(zi_gnn *net, const float *params);
+zi_status zi_gnn_get_params(const zi_gnn *net, float *params);
+/* y (n_nodes) = prediction for features X (n_nodes x dims[0], row-major). */
+zi_status zi_gnn_forward(zi_gnn *net, const float *X, float *y, void *hip_stream);
+/* Forward, loss sum (y - t)^2 / sum t^2 (HOST *loss) and backward; the
+ * gradients stay on the device for zi_gnn_adam_step and are also copied to
+ * grads (HOST, zi_gnn_param_count entries) when it is not NULL. */
+zi_status zi_gnn_loss_grad(zi_gnn *net, const float *X, const float *t, double *loss,
+                           float *grads, void *hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradients. */
+zi_status zi_gnn_adam_step(zi_gnn *net, float lr, void *hip_stream);
+void zi_gnn_destroy(zi_gnn *net);
+
+/* Measurement aid: copies n float64 values (n even, 16-byte aligned) from
+ * src to dst with the 16-byte streaming accesses of the solver kernels and
+ * returns the event-timed kernel milliseconds in *ms (HOST, may be NULL).
+ * Used as the plain copy of known size that calibrates HBM counters. */
+zi_status zi_copy_probe(const double *src, double *dst, int64_t n, double *ms, void *hip_stream);
 
 /* Number of SpMM tile configurations and a description of tile t. */
 int32_t zi_tile_count(void);

@@ -16,7 +16,9 @@ slow and written to be checked against the paper by eye:
                    reciprocity check that solves the full block system;
 * ``sphere``    -- the closed-form multilayer-sphere dipole potential used to
                    pin the oracle against physics;
-* ``eit``       -- the linearized EIT lead field of App. A.3.
+* ``eit``       -- the linearized EIT lead field of App. A.3;
+* ``gnn``       -- the mesh-graph network of the learned PCG warm start
+                   (forward, backward, Adam), the reference for its kernels.
 
 Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import it.  The product library never calls it, and it shares
@@ -27,4 +29,4 @@ Parity status of each function is stated in its docstring; every function is
 pinned by a ``-m "not gpu"`` test in ``tests/test_oracle_*.py``.
 """
 
-from . import fem, source, solve, leadfield, sphere, eit  # noqa: F401
+from . import fem, source, solve, leadfield, sphere, eit, gnn  # noqa: F401

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libzi.so")
-SOURCES = ["zi_api.hip", "k_util.hip", "k_assemble.hip", "k_pcg.hip", "k_leadfield.hip"]
+SOURCES = ["zi_api.hip", "k_util.hip", "k_assemble.hip", "k_pcg.hip", "k_leadfield.hip",
+           "k_gnn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("ZI_OFFLOAD_ARCH", "gfx950")
 

@@ -35,16 +35,56 @@ constexpr int BLOCK = 256;           // 4 waves
 constexpr int TARGET_BLOCKS = 2048;  // row tiles x column chunks per launch
 
 struct Geom {
-    int n, ldp, rb, nrt, ncc, nb, nb_pad;
+    int n, ldp, ncc;      // rows, padded columns, column chunks
+    int front;            // 0: each block owns a row chunk; 1: cooperative front
+    int rb;               // chunk schedule: rows per block
+    int P, B, U;          // front schedule: row parts, blocks per unit, units
+    int nrt;              // partial-sum rows per column
+    int nb, nb_pad;       // blocks (nb_pad: launched, a multiple of 8)
 };
 
-__device__ __forceinline__ bool block_tile(const Geom &g, int &cc, int &rt) {
+// Rows a block visits: base = rs + first + j * stride (base < re); the block's
+// lanes take rows base + slot.  prow indexes the block's partial sums.
+struct Sched {
+    int cc, rs, re, first, stride, prow;
+};
+
+// Hardware block b runs on XCD b mod 8.  Blocks are numbered so that each XCD
+// receives contiguous work:
+//  * chunk schedule: logical tile (b mod 8) * nb_pad/8 + b/8 covers (column
+//    chunk, row chunk) pairs in order, so an XCD gets consecutive rows;
+//  * front schedule: each XCD owns units (column chunk, row part); the B
+//    blocks of a unit walk its row range together as one front (block k takes
+//    row groups k, k + B, ...), so rows that share neighbours are processed
+//    close in time on the same XCD and their reuse stays in its L2.
+template <int RSTEP>
+__device__ __forceinline__ bool block_sched(const Geom &g, Sched &sc) {
     const int b = blockIdx.x;
-    const int per = g.nb_pad >> 3;
-    const int logical = (b & 7) * per + (b >> 3);
-    if (logical >= g.nb) return false;
-    cc = logical / g.nrt;
-    rt = logical - cc * g.nrt;
+    if (!g.front) {
+        const int per = g.nb_pad >> 3;
+        const int logical = (b & 7) * per + (b >> 3);
+        if (logical >= g.nb) return false;
+        sc.cc = logical / g.nrt;
+        const int rt = logical - sc.cc * g.nrt;
+        sc.rs = rt * g.rb;
+        sc.re = min(g.n, sc.rs + g.rb);
+        sc.first = 0;
+        sc.stride = RSTEP;
+        sc.prow = rt;
+        return true;
+    }
+    const int x = b & 7, j = b >> 3;
+    const int m = j / g.B, k = j - m * g.B;
+    const int u = x + 8 * m;
+    if (u >= g.U) return false;
+    sc.cc = u / g.P;
+    const int pr = u - sc.cc * g.P;
+    const int part = (g.n + g.P - 1) / g.P;
+    sc.rs = pr * part;
+    sc.re = min(g.n, sc.rs + part);
+    sc.first = k * RSTEP;
+    sc.stride = g.B * RSTEP;
+    sc.prow = pr * g.B + k;
     return true;
 }
 
@@ -184,7 +224,7 @@ __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
 // column-major: part[q][col * nrt + rt].
 template <int LPR, int NV, int NQ>
 __device__ __forceinline__ void block_partials(const Geom &g, const Lane<LPR, NV> &ln, int cc,
-                                               int rt, const double2 (&acc)[NQ][NV],
+                                               int prow, const double2 (&acc)[NQ][NV],
                                                double *const (&part)[NQ]) {
     constexpr int RS = Lane<LPR, NV>::RSTEP;
     constexpr int CW = Lane<LPR, NV>::CW;
@@ -204,7 +244,7 @@ __device__ __forceinline__ void block_partials(const Geom &g, const Lane<LPR, NV
         if (col < g.ldp) {
             double s = 0.0;
             for (int k = 0; k < RS; ++k) s += red[q][k][cl];
-            part[q][(size_t)col * g.nrt + rt] = s;
+            part[q][(size_t)col * g.nrt + prow] = s;
         }
     }
 }
@@ -219,15 +259,15 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
                                                 const T *__restrict__ X, T *__restrict__ Y,
                                                 double *part) {
     using PT = Pair<T>;
-    int cc, rt;
-    if (!block_tile(g, cc, rt)) return;
-    Lane<LPR, NV> ln(g, cc);
+    Sched sc;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
+    Lane<LPR, NV> ln(g, sc.cc);
     double2 dotacc[1][NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) dotacc[0][v] = make_double2(0.0, 0.0);
-    const int r0 = rt * g.rb;
-    const int r1 = min(g.n, r0 + g.rb);
-    for (int row = r0 + ln.slot; row < r1; row += Lane<LPR, NV>::RSTEP) {
+    for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
+        const int row = base + ln.slot;
+        if (row >= sc.re) continue;
         typename PT::type acc[NV];
         row_product<LPR, NV, T>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc);
 #pragma unroll
@@ -244,25 +284,23 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
     }
     if (WITH_DOT) {
         double *const parts[1] = {part};
-        block_partials<LPR, NV, 1>(g, ln, cc, rt, dotacc, parts);
+        block_partials<LPR, NV, 1>(g, ln, sc.cc, sc.prow, dotacc, parts);
     }
 }
 
 constexpr int UNROLL = 4;   // rows per lane per step in the streaming kernels
 
-// X += alpha P, R -= alpha Q; partials r.D^-1 r and r.r of the new R.
+// R -= alpha Q; partials r.D^-1 r and r.r of the new R.  (X is updated
+// lazily by k_xflush from the ring of the last LAZY search directions.)
 template <int LPR, int NV, class TP>
 __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restrict__ alpha,
                                                   const double *__restrict__ dinv,
-                                                  double *__restrict__ X,
                                                   double *__restrict__ R,
-                                                  const TP *__restrict__ P,
                                                   const TP *__restrict__ Q, double *prz,
                                                   double *prr) {
-    int cc, rt;
-    if (!block_tile(g, cc, rt)) return;
-    Lane<LPR, NV> ln(g, cc);
-    constexpr int RS = Lane<LPR, NV>::RSTEP;
+    Sched sc;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
+    Lane<LPR, NV> ln(g, sc.cc);
     double2 acc[2][NV];
     double2 al[NV];
 #pragma unroll
@@ -270,40 +308,33 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
         acc[0][v] = acc[1][v] = make_double2(0.0, 0.0);
         al[v] = ln.ok[v] ? ld2(alpha + ln.c[v]) : make_double2(0.0, 0.0);
     }
-    const int r0 = rt * g.rb;
-    const int r1 = min(g.n, r0 + g.rb);
-    for (int base = r0 + ln.slot; base < r1; base += UNROLL * RS) {
-        double2 x[UNROLL][NV], r[UNROLL][NV], p[UNROLL][NV], q[UNROLL][NV];
+    const int r1 = sc.re;
+    for (int base = sc.rs + sc.first + ln.slot; base - ln.slot < r1; base += UNROLL * sc.stride) {
+        double2 r[UNROLL][NV], q[UNROLL][NV];
         double di[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int row = base + u * RS;
+            const int row = base + u * sc.stride;
             const bool rv = row < r1;
             di[u] = rv ? dinv[row] : 0.0;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const size_t o = (size_t)row * g.ldp + ln.c[v];
                 const bool on = rv && ln.ok[v];
-                x[u][v] = on ? ld2(X + o) : make_double2(0.0, 0.0);
                 r[u][v] = on ? ld2(R + o) : make_double2(0.0, 0.0);
-                p[u][v] = on ? ld2(P + o) : make_double2(0.0, 0.0);
                 q[u][v] = on ? ld2(Q + o) : make_double2(0.0, 0.0);
             }
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int row = base + u * RS;
+            const int row = base + u * sc.stride;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 if (!(row < r1 && ln.ok[v])) continue;
-                const size_t o = (size_t)row * g.ldp + ln.c[v];
-                double2 xx = x[u][v], rr = r[u][v];
-                xx.x = fma(al[v].x, p[u][v].x, xx.x);
-                xx.y = fma(al[v].y, p[u][v].y, xx.y);
+                double2 rr = r[u][v];
                 rr.x = fma(-al[v].x, q[u][v].x, rr.x);
                 rr.y = fma(-al[v].y, q[u][v].y, rr.y);
-                st2(X + o, xx);
-                st2(R + o, rr);
+                st2(R + (size_t)row * g.ldp + ln.c[v], rr);
                 acc[0][v].x = fma(rr.x, rr.x * di[u], acc[0][v].x);
                 acc[0][v].y = fma(rr.y, rr.y * di[u], acc[0][v].y);
                 acc[1][v].x = fma(rr.x, rr.x, acc[1][v].x);
@@ -312,31 +343,74 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
         }
     }
     double *const parts[2] = {prz, prr};
-    block_partials<LPR, NV, 2>(g, ln, cc, rt, acc, parts);
+    block_partials<LPR, NV, 2>(g, ln, sc.cc, sc.prow, acc, parts);
 }
 
-// P = D^-1 R + beta P (beta == nullptr: P = D^-1 R).
+// Ring of the last LAZY search directions and their step lengths.
+constexpr int LAZY = 4;
+template <class TP>
+struct Ring {
+    const TP *p[LAZY];
+};
+
+// X += sum_{j < cnt} alpha_j P_j (in ring order: the iterations' order).
+template <int LPR, int NV, class TP>
+__global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double *__restrict__ alphas,
+                                                  Ring<TP> ring, double *__restrict__ X) {
+    Sched sc;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
+    Lane<LPR, NV> ln(g, sc.cc);
+    double2 al[LAZY][NV];
+#pragma unroll
+    for (int j = 0; j < LAZY; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            al[j][v] = (j < cnt && ln.ok[v]) ? ld2(alphas + (size_t)j * g.ldp + ln.c[v])
+                                             : make_double2(0.0, 0.0);
+    for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
+        const int row = base + ln.slot;
+        if (row >= sc.re) continue;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (!ln.ok[v]) continue;
+            const size_t o = (size_t)row * g.ldp + ln.c[v];
+            double2 p[LAZY];
+#pragma unroll
+            for (int j = 0; j < LAZY; ++j) p[j] = j < cnt ? ld2(ring.p[j] + o) : make_double2(0.0, 0.0);
+            double2 x = ld2(X + o);
+#pragma unroll
+            for (int j = 0; j < LAZY; ++j) {
+                if (j < cnt) {
+                    x.x = fma(al[j][v].x, p[j].x, x.x);
+                    x.y = fma(al[j][v].y, p[j].y, x.y);
+                }
+            }
+            st2(X + o, x);
+        }
+    }
+}
+
+// Pout = D^-1 R + beta Pin (beta == nullptr: Pout = D^-1 R).
 template <int LPR, int NV, class TP>
 __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restrict__ beta,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ R,
-                                                   TP *__restrict__ P) {
-    int cc, rt;
-    if (!block_tile(g, cc, rt)) return;
-    Lane<LPR, NV> ln(g, cc);
-    constexpr int RS = Lane<LPR, NV>::RSTEP;
+                                                   const TP *__restrict__ P,
+                                                   TP *__restrict__ Pout) {
+    Sched sc;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
+    Lane<LPR, NV> ln(g, sc.cc);
     double2 be[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
         be[v] = (ln.ok[v] && beta) ? ld2(beta + ln.c[v]) : make_double2(0.0, 0.0);
-    const int r0 = rt * g.rb;
-    const int r1 = min(g.n, r0 + g.rb);
-    for (int base = r0 + ln.slot; base < r1; base += UNROLL * RS) {
+    const int r1 = sc.re;
+    for (int base = sc.rs + sc.first + ln.slot; base - ln.slot < r1; base += UNROLL * sc.stride) {
         double2 r[UNROLL][NV], p[UNROLL][NV];
         double di[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int row = base + u * RS;
+            const int row = base + u * sc.stride;
             const bool rv = row < r1;
             di[u] = rv ? dinv[row] : 0.0;
 #pragma unroll
@@ -349,7 +423,7 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int row = base + u * RS;
+            const int row = base + u * sc.stride;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 if (!(row < r1 && ln.ok[v])) continue;
@@ -360,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
                 } else {
                     pn = make_double2(r[u][v].x * di[u], r[u][v].y * di[u]);
                 }
-                st2(P + (size_t)row * g.ldp + ln.c[v], pn);
+                st2(Pout + (size_t)row * g.ldp + ln.c[v], pn);
             }
         }
     }
@@ -372,19 +446,20 @@ template <int LPR, int NV>
 __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__restrict__ bp,
                                                     const int32_t *__restrict__ bc,
                                                     const double *__restrict__ bv,
+                                                    const int32_t *__restrict__ colmap,
                                                     const double *__restrict__ dinv,
                                                     const double *__restrict__ Q,
                                                     double *__restrict__ R, double *pbb,
                                                     double *prz, double *prr) {
-    int cc, rt;
-    if (!block_tile(g, cc, rt)) return;
-    Lane<LPR, NV> ln(g, cc);
+    Sched sc;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
+    Lane<LPR, NV> ln(g, sc.cc);
     double2 acc[3][NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[0][v] = acc[1][v] = acc[2][v] = make_double2(0.0, 0.0);
-    const int r0 = rt * g.rb;
-    const int r1 = min(g.n, r0 + g.rb);
-    for (int row = r0 + ln.slot; row < r1; row += Lane<LPR, NV>::RSTEP) {
+    for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
+        const int row = base + ln.slot;
+        if (row >= sc.re) continue;
         const double di = dinv[row];
         const int s = bp[row], e = bp[row + 1];
 #pragma unroll
@@ -392,7 +467,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__res
             if (!ln.ok[v]) continue;
             double2 b = make_double2(0.0, 0.0);
             for (int k = s; k < e; ++k) {
-                const int l = bc[k];
+                const int l = colmap ? colmap[bc[k]] : bc[k];
                 if (l == ln.c[v]) b.x = bv[k];
                 if (l == ln.c[v] + 1) b.y = bv[k];
             }
@@ -413,7 +488,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__res
         }
     }
     double *const parts[3] = {pbb, prz, prr};
-    block_partials<LPR, NV, 3>(g, ln, cc, rt, acc, parts);
+    block_partials<LPR, NV, 3>(g, ln, sc.cc, sc.prow, acc, parts);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,10 +496,14 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__res
 
 struct Scal {
     double *rho, *alpha, *beta, *bb, *rr;
+    double *tt;                       // per-column stop level for ||r||^2
     int32_t *iters, *active, *flag;   // flag[0]: breakdown
 };
 
 constexpr int RED = 256;
+
+// Default interval of the reliable updates of the mixed-precision solve.
+constexpr int MIXED_CHECK = 16;
 
 __device__ __forceinline__ double col_sum(const double *part, int nrt, int c) {
     __shared__ double s[RED];
@@ -441,9 +520,12 @@ __device__ __forceinline__ double col_sum(const double *part, int nrt, int c) {
     return r;
 }
 
+// tt = max(tol^2 ||b||^2, eta^2 ||r||^2): eta = 0 runs to the tolerance; the
+// mixed-precision mode uses eta > 0 so that each float32 cycle only reduces
+// its starting residual by eta before the FP64 refinement step.
 __global__ __launch_bounds__(RED) void k_red_init(Scal sc, const double *pbb, const double *prz,
                                                   const double *prr, int nrt, int L,
-                                                  double tol2) {
+                                                  double tol2, double eta2) {
     const int c = blockIdx.x;
     const double bb = col_sum(pbb, nrt, c);
     const double rz = col_sum(prz, nrt, c);
@@ -452,6 +534,7 @@ __global__ __launch_bounds__(RED) void k_red_init(Scal sc, const double *pbb, co
         sc.bb[c] = bb;
         sc.rho[c] = rz;
         sc.rr[c] = rr;
+        sc.tt[c] = fmax(tol2 * bb, eta2 * rr);
         sc.iters[c] = 0;
         sc.alpha[c] = 0.0;
         sc.beta[c] = 0.0;
@@ -459,7 +542,8 @@ __global__ __launch_bounds__(RED) void k_red_init(Scal sc, const double *pbb, co
     }
 }
 
-__global__ __launch_bounds__(RED) void k_red_alpha(Scal sc, const double *ppq, int nrt) {
+__global__ __launch_bounds__(RED) void k_red_alpha(Scal sc, double *alpha, const double *ppq,
+                                                   int nrt) {
     const int c = blockIdx.x;
     const double pq = col_sum(ppq, nrt, c);
     if (threadIdx.x == 0) {
@@ -472,12 +556,12 @@ __global__ __launch_bounds__(RED) void k_red_alpha(Scal sc, const double *ppq, i
                 sc.flag[0] = 1;
             }
         }
-        sc.alpha[c] = a;
+        alpha[c] = a;
     }
 }
 
 __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, const double *prr,
-                                                  int nrt, double tol2) {
+                                                  int nrt) {
     const int c = blockIdx.x;
     const double rz = col_sum(prz, nrt, c);
     const double rr = col_sum(prr, nrt, c);
@@ -486,7 +570,7 @@ __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, co
         if (sc.active[c]) {
             sc.iters[c] += 1;
             sc.rr[c] = rr;
-            if (rr <= tol2 * sc.bb[c]) {
+            if (rr <= sc.tt[c]) {
                 sc.active[c] = 0;
             } else {
                 b = rz / sc.rho[c];
@@ -501,7 +585,7 @@ __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, co
 // columns whose true residual misses the tolerance restart with P = D^-1 R.
 __global__ __launch_bounds__(RED) void k_red_refine(Scal sc, const double *prz,
                                                     const double *prr, int nrt, int L,
-                                                    double tol2) {
+                                                    double tol2, double eta2) {
     const int c = blockIdx.x;
     const double rz = col_sum(prz, nrt, c);
     const double rr = col_sum(prr, nrt, c);
@@ -509,7 +593,10 @@ __global__ __launch_bounds__(RED) void k_red_refine(Scal sc, const double *prz,
         const int again = (c < L && sc.bb[c] > 0.0 && rr > tol2 * sc.bb[c]) ? 1 : 0;
         sc.active[c] = again;
         sc.rr[c] = rr;
-        if (again) sc.rho[c] = rz;
+        if (again) {
+            sc.rho[c] = rz;
+            sc.tt[c] = fmax(tol2 * sc.bb[c], eta2 * rr);
+        }
         sc.alpha[c] = 0.0;
         sc.beta[c] = 0.0;
     }
@@ -525,36 +612,43 @@ __global__ __launch_bounds__(RED) void k_red_sum(const double *part, int nrt, do
 // Tile table and dispatch
 
 struct TileCfg {
-    int lpr, nv;
+    int lpr, nv, front;
     const char *name;
 };
 
 const TileCfg kTiles[] = {
-    {64, 1, "lpr64_nv1_cw128"}, {64, 2, "lpr64_nv2_cw256"}, {32, 1, "lpr32_nv1_cw64"},
-    {32, 2, "lpr32_nv2_cw128"}, {16, 1, "lpr16_nv1_cw32"},  {16, 2, "lpr16_nv2_cw64"},
-    {8, 1, "lpr8_nv1_cw16"},    {8, 2, "lpr8_nv2_cw32"},    {4, 1, "lpr4_nv1_cw8"},
-    {64, 4, "lpr64_nv4_cw512"},
+    {64, 1, 0, "lpr64_nv1_cw128"},       {64, 2, 0, "lpr64_nv2_cw256"},
+    {32, 1, 0, "lpr32_nv1_cw64"},        {32, 2, 0, "lpr32_nv2_cw128"},
+    {16, 1, 0, "lpr16_nv1_cw32"},        {16, 2, 0, "lpr16_nv2_cw64"},
+    {8, 1, 0, "lpr8_nv1_cw16"},          {8, 2, 0, "lpr8_nv2_cw32"},
+    {4, 1, 0, "lpr4_nv1_cw8"},           {64, 4, 0, "lpr64_nv4_cw512"},
+    {64, 1, 1, "lpr64_nv1_cw128_front"}, {64, 2, 1, "lpr64_nv2_cw256_front"},
+    {32, 1, 1, "lpr32_nv1_cw64_front"},  {32, 2, 1, "lpr32_nv2_cw128_front"},
+    {16, 1, 1, "lpr16_nv1_cw32_front"},  {16, 2, 1, "lpr16_nv2_cw64_front"},
+    {8, 1, 1, "lpr8_nv1_cw16_front"},    {8, 2, 1, "lpr8_nv2_cw32_front"},
 };
 constexpr int NTILES = sizeof(kTiles) / sizeof(kTiles[0]);
 
 #define ZI_TILE_SWITCH(tile, FN, ...)                       \
-    switch (tile) {                                         \
-        case 0: FN<64, 1>(__VA_ARGS__); break;              \
-        case 1: FN<64, 2>(__VA_ARGS__); break;              \
-        case 2: FN<32, 1>(__VA_ARGS__); break;              \
-        case 3: FN<32, 2>(__VA_ARGS__); break;              \
-        case 4: FN<16, 1>(__VA_ARGS__); break;              \
-        case 5: FN<16, 2>(__VA_ARGS__); break;              \
-        case 6: FN<8, 1>(__VA_ARGS__); break;               \
-        case 7: FN<8, 2>(__VA_ARGS__); break;               \
-        case 8: FN<4, 1>(__VA_ARGS__); break;               \
+    switch (kTiles[tile].lpr * 8 + kTiles[tile].nv) {       \
+        case 64 * 8 + 1: FN<64, 1>(__VA_ARGS__); break;     \
+        case 64 * 8 + 2: FN<64, 2>(__VA_ARGS__); break;     \
+        case 32 * 8 + 1: FN<32, 1>(__VA_ARGS__); break;     \
+        case 32 * 8 + 2: FN<32, 2>(__VA_ARGS__); break;     \
+        case 16 * 8 + 1: FN<16, 1>(__VA_ARGS__); break;     \
+        case 16 * 8 + 2: FN<16, 2>(__VA_ARGS__); break;     \
+        case 8 * 8 + 1: FN<8, 1>(__VA_ARGS__); break;       \
+        case 8 * 8 + 2: FN<8, 2>(__VA_ARGS__); break;       \
+        case 4 * 8 + 1: FN<4, 1>(__VA_ARGS__); break;       \
         default: FN<64, 4>(__VA_ARGS__); break;             \
     }
 
 int auto_tile(int ldp) {
-    // narrowest single chunk that holds every column, else the widest tile
+    // narrowest single chunk (chunk schedule) that holds every column, else
+    // the widest tile
     int best = -1, bestcw = 1 << 30;
     for (int t = 0; t < NTILES; ++t) {
+        if (kTiles[t].front) continue;
         const int cw = 2 * kTiles[t].lpr * kTiles[t].nv;
         if (cw >= ldp && cw < bestcw) {
             best = t;
@@ -568,20 +662,34 @@ Geom make_geom(int n, int ldp, int tile) {
     const TileCfg &t = kTiles[tile];
     const int cw = 2 * t.lpr * t.nv;
     const int rstep = 4 * (64 / t.lpr);
-    Geom g;
+    Geom g{};
     g.n = n;
     g.ldp = ldp;
     g.ncc = (ldp + cw - 1) / cw;
-    int nrt_target = TARGET_BLOCKS / g.ncc;
-    if (nrt_target < 1) nrt_target = 1;
-    int rb = (n + nrt_target - 1) / nrt_target;
-    rb = ((rb + rstep - 1) / rstep) * rstep;
-    if (rb < rstep) rb = rstep;
-    g.rb = rb;
-    g.nrt = (n + rb - 1) / rb;
-    if (g.nrt < 1) g.nrt = 1;
-    g.nb = g.ncc * g.nrt;
-    g.nb_pad = ((g.nb + 7) / 8) * 8;
+    g.front = t.front;
+    if (!t.front) {
+        int nrt_target = TARGET_BLOCKS / g.ncc;
+        if (nrt_target < 1) nrt_target = 1;
+        int rb = (n + nrt_target - 1) / nrt_target;
+        rb = ((rb + rstep - 1) / rstep) * rstep;
+        if (rb < rstep) rb = rstep;
+        g.rb = rb;
+        g.nrt = (n + rb - 1) / rb;
+        if (g.nrt < 1) g.nrt = 1;
+        g.nb = g.ncc * g.nrt;
+        g.nb_pad = ((g.nb + 7) / 8) * 8;
+    } else {
+        g.P = g.ncc >= 8 ? 1 : 8 / g.ncc;          // row parts per column chunk
+        g.U = g.ncc * g.P;                         // units (chunk, part)
+        const int groups = (n + g.P - 1) / g.P / rstep + 1;   // row groups per unit
+        int B = TARGET_BLOCKS / g.U;
+        if (B < 1) B = 1;
+        if (B > groups) B = groups;
+        g.B = B;
+        g.nrt = g.P * B;
+        g.nb = ((g.U + 7) / 8) * 8 * B;            // units padded to XCD multiples
+        g.nb_pad = g.nb;
+    }
     return g;
 }
 
@@ -598,23 +706,31 @@ void launch_spmm(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t 
 
 template <int LPR, int NV, class TP>
 void launch_update(const Geom &g, hipStream_t s, const double *alpha, const double *dinv,
-                   double *X, double *R, const TP *P, const TP *Q, double *prz, double *prr) {
+                   double *R, const TP *Q, double *prz, double *prr) {
     hipLaunchKernelGGL((k_update<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, alpha, dinv,
-                       X, R, P, Q, prz, prr);
+                       R, Q, prz, prr);
 }
 
 template <int LPR, int NV, class TP>
 void launch_pupdate(const Geom &g, hipStream_t s, const double *beta, const double *dinv,
-                    const double *R, TP *P) {
+                    const double *R, const TP *P, TP *Pout) {
     hipLaunchKernelGGL((k_pupdate<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, beta, dinv,
-                       R, P);
+                       R, P, Pout);
+}
+
+template <int LPR, int NV, class TP>
+void launch_xflush(const Geom &g, hipStream_t s, int cnt, const double *alphas, Ring<TP> ring,
+                   double *X) {
+    hipLaunchKernelGGL((k_xflush<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
+                       ring, X);
 }
 
 template <int LPR, int NV>
-void launch_residual(const Geom &g, hipStream_t s, const zi_system *sys, const double *dinv,
-                     const double *Q, double *R, double *pbb, double *prz, double *prr) {
+void launch_residual(const Geom &g, hipStream_t s, const zi_system *sys, const int32_t *colmap,
+                     const double *dinv, const double *Q, double *R, double *pbb, double *prz,
+                     double *prr) {
     hipLaunchKernelGGL((k_residual<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, sys->b_ptr,
-                       sys->b_col, sys->b_val, dinv, Q, R, pbb, prz, prr);
+                       sys->b_col, sys->b_val, colmap, dinv, Q, R, pbb, prz, prr);
 }
 
 __global__ void k_to_f32(const double *a, int64_t n, float *b) {
@@ -634,9 +750,12 @@ __global__ void k_dinv(const double *d, int32_t n, double *dinv) {
 
 struct zi_solver_ws {
     int ldp = 0, nrt_cap = 0;
-    double *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr, *dinv = nullptr;
+    double *X = nullptr, *R = nullptr, *Q = nullptr, *dinv = nullptr;
+    double *P[LAZY] = {nullptr, nullptr, nullptr, nullptr};   // search-direction ring
+    double *aring = nullptr;                                  // LAZY x ldp step lengths
+    double *aflush = nullptr;                                 // LAZY x ldp scratch
     double *part[3] = {nullptr, nullptr, nullptr};
-    double *sc_d = nullptr;     // rho alpha beta bb rr (5 ldp)
+    double *sc_d = nullptr;     // rho alpha beta bb rr tt (6 ldp)
     int32_t *sc_i = nullptr;    // iters active (2 ldp) + flag
     std::vector<hipEvent_t> ev;
     zi::Pool pool;
@@ -664,10 +783,18 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
     ws = new zi_solver_ws();
     const size_t blk = (size_t)sys->n * ldp;
     zi_status st = ZI_OK;
+    for (int j = 0; j < LAZY; ++j) {
+        if ((st = ws->pool.alloc(&ws->P[j], blk)) != ZI_OK) {
+            delete ws;
+            return st;
+        }
+    }
     if ((st = ws->pool.alloc(&ws->X, blk)) != ZI_OK || (st = ws->pool.alloc(&ws->R, blk)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->P, blk)) != ZI_OK || (st = ws->pool.alloc(&ws->Q, blk)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->aring, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->aflush, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->Q, blk)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->dinv, (size_t)sys->n)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->sc_d, (size_t)5 * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->sc_d, (size_t)6 * ldp)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->sc_i, (size_t)2 * ldp + 1)) != ZI_OK) {
         delete ws;
         return st;
@@ -719,19 +846,24 @@ struct SolveCtx {
     Geom g{};
     int tile = 0, ldp = 0, L = 0, maxit = 0, check = 0;
     double tol = 0, tol2 = 0;
+    double eta2 = 0;          // inner-cycle reduction (squared); 0 = run to tol
     bool mixed = false, timing = false;
     Scal sc{};
     EventTimer timer{nullptr};
-    std::vector<hipEvent_t> ev_spmm, ev_upd;
+    // event pairs per timed kernel: spmm_pq, update, pupdate, xflush
+    std::vector<hipEvent_t> ev[4];
     int it = 0;               // iterations of the block loop so far
+    int flushed = 0;          // iterations whose steps are already in X
     int refinements = 0;
+    int32_t *colmap = nullptr;   // electrode -> solved column (or -1), if a subset
     bool any_active = true;
     bool done = false;        // no further iterations wanted
     int32_t h_flag = 0;
     std::vector<int32_t> h_active;
     std::chrono::steady_clock::time_point t_start;
-    float *P32() const { return reinterpret_cast<float *>(ws->P); }
-    float *Q32() const { return reinterpret_cast<float *>(ws->Q); }
+    template <class TP>
+    TP *P(int k) const { return reinterpret_cast<TP *>(ws->P[k % LAZY]); }
+    double *alpha(int k) const { return ws->aring + (size_t)(k % LAZY) * ldp; }
 };
 
 zi_status read_active(SolveCtx &c, hipStream_t s) {
@@ -744,74 +876,140 @@ zi_status read_active(SolveCtx &c, hipStream_t s) {
     return ZI_OK;
 }
 
-// Enqueue one PCG iteration (5 kernels, no host synchronisation).  TP is the
-// element type of P and of Q = A P; the matrix values have the same type.
+struct Timed {
+    SolveCtx &c;
+    int which;
+    hipStream_t s;
+    hipEvent_t e1 = nullptr;
+    zi_status st = ZI_OK;
+    Timed(SolveCtx &c_, int w, hipStream_t s_) : c(c_), which(w), s(s_) {
+        if (!c.timing) return;
+        hipEvent_t e0;
+        if ((st = c.timer.get(&e0)) != ZI_OK || (st = c.timer.get(&e1)) != ZI_OK) return;
+        c.ev[which].push_back(e0);
+        c.ev[which].push_back(e1);
+        (void)hipEventRecord(e0, s);
+    }
+    ~Timed() {
+        if (c.timing && e1) (void)hipEventRecord(e1, s);
+    }
+};
+
+zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r);
+
+// X += sum of the pending steps alpha_j P_j (iterations flushed .. it_end-1).
 template <class TP>
-zi_status enqueue_iteration(SolveCtx &c, const TP *va, TP *P, TP *Q, hipStream_t s) {
+zi_status enqueue_flush(SolveCtx &c, int it_end, hipStream_t s) {
+    const int cnt = it_end - c.flushed;
+    if (cnt <= 0) return ZI_OK;
+    Ring<TP> ring;
+    for (int j = 0; j < LAZY; ++j) ring.p[j] = c.P<TP>(c.flushed + j);
+    // the alpha slots of iterations flushed.. are (flushed + j) % LAZY; the
+    // ring is rotated so that entry j is iteration flushed + j
+    double *al = c.ws->aring;
+    const int first = c.flushed % LAZY;
+    {
+        Timed t(c, 3, s);
+        ZI_TRY(t.st);
+        if (first == 0) {
+            ZI_TILE_SWITCH(c.tile, launch_xflush, c.g, s, cnt, (const double *)al, ring, c.ws->X);
+        } else {
+            // the step lengths are rotated into a contiguous scratch block
+            for (int j = 0; j < cnt; ++j)
+                ZI_HIP(hipMemcpyAsync(c.ws->aflush + (size_t)j * c.ldp, c.alpha(c.flushed + j),
+                                      sizeof(double) * c.ldp, hipMemcpyDeviceToDevice, s));
+            ZI_TILE_SWITCH(c.tile, launch_xflush, c.g, s, cnt, (const double *)c.ws->aflush, ring,
+                           c.ws->X);
+        }
+    }
+    ZI_HIP(hipGetLastError());
+    c.flushed = it_end;
+    return ZI_OK;
+}
+
+// Enqueue iteration k (no host synchronisation): SpMM with p.q, alpha, the
+// residual update, every LAZY-th iteration the X flush, beta and the next
+// direction into the ring.  TP is the element type of P and Q (the matrix
+// values have the same type).  replace_r: after the flush, overwrite r by the
+// FP64 true residual b - A x before beta (a reliable update: the search
+// direction is kept, only the drift of the recurrence is removed).
+template <class TP>
+zi_status enqueue_iteration(SolveCtx &c, int k, const TP *va, hipStream_t s, bool replace_r) {
     zi_solver_ws *ws = c.ws;
     const Geom &g = c.g;
     const int tile = c.tile;
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
-    if (c.timing) {
-        ZI_TRY(c.timer.get(&e0));
-        ZI_TRY(c.timer.get(&e1));
-        ZI_HIP(hipEventRecord(e0, s));
+    TP *Pk = c.P<TP>(k), *Pn = c.P<TP>(k + 1);
+    TP *Q = reinterpret_cast<TP *>(ws->Q);
+    double *al = c.alpha(k);
+    {
+        Timed t(c, 0, s);
+        ZI_TRY(t.st);
+        ZI_TILE_SWITCH(tile, launch_spmm, g, s, c.sys->sp_ptr, c.sys->sp_col, va, (const TP *)Pk,
+                       Q, ws->part[0]);
     }
-    ZI_TILE_SWITCH(tile, launch_spmm, g, s, c.sys->sp_ptr, c.sys->sp_col, va, (const TP *)P, Q,
-                   ws->part[0]);
-    if (c.timing) ZI_HIP(hipEventRecord(e1, s));
-    hipLaunchKernelGGL(k_red_alpha, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[0], g.nrt);
-    if (c.timing) {
-        ZI_TRY(c.timer.get(&e2));
-        ZI_TRY(c.timer.get(&e3));
-        ZI_HIP(hipEventRecord(e2, s));
+    hipLaunchKernelGGL(k_red_alpha, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt);
+    {
+        Timed t(c, 1, s);
+        ZI_TRY(t.st);
+        ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)al, (const double *)ws->dinv,
+                       ws->R, (const TP *)Q, ws->part[1], ws->part[2]);
     }
-    ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)c.sc.alpha, (const double *)ws->dinv,
-                   ws->X, ws->R, (const TP *)P, (const TP *)Q, ws->part[1], ws->part[2]);
-    if (c.timing) {
-        ZI_HIP(hipEventRecord(e3, s));
-        c.ev_spmm.push_back(e0);
-        c.ev_spmm.push_back(e1);
-        c.ev_upd.push_back(e2);
-        c.ev_upd.push_back(e3);
-    }
+    if ((k + 1) % LAZY == 0 || replace_r) ZI_TRY(enqueue_flush<TP>(c, k + 1, s));
+    if (replace_r) ZI_TRY(true_residual(c, s, true));
     hipLaunchKernelGGL(k_red_beta, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[1], ws->part[2],
-                       g.nrt, c.tol2);
-    ZI_TILE_SWITCH(tile, launch_pupdate, g, s, (const double *)c.sc.beta, (const double *)ws->dinv,
-                   (const double *)ws->R, P);
+                       g.nrt);
+    {
+        Timed t(c, 2, s);
+        ZI_TRY(t.st);
+        ZI_TILE_SWITCH(tile, launch_pupdate, g, s, (const double *)c.sc.beta,
+                       (const double *)ws->dinv, (const double *)ws->R, (const TP *)Pk, Pn);
+    }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
 }
 
+// Iterations it .. it+count-1.  In the mixed-precision mode the last
+// iteration of every chunk is a reliable update.
 zi_status enqueue_iterations(SolveCtx &c, int count, hipStream_t s) {
-    for (int k = 0; k < count; ++k) {
+    const int it0 = c.it;
+    for (int j = 0; j < count; ++j) {
         if (c.mixed) {
-            ZI_TRY(enqueue_iteration<float>(c, c.sys->sp_val32, c.P32(), c.Q32(), s));
+            ZI_TRY(enqueue_iteration<float>(c, it0 + j, c.sys->sp_val32, s, j == count - 1));
         } else {
-            ZI_TRY(enqueue_iteration<double>(c, c.sys->sp_val, c.ws->P, c.ws->Q, s));
+            ZI_TRY(enqueue_iteration<double>(c, it0 + j, c.sys->sp_val, s, false));
         }
     }
     return ZI_OK;
 }
 
+zi_status flush_all(SolveCtx &c, hipStream_t s) {
+    if (c.mixed) return enqueue_flush<float>(c, c.it, s);
+    return enqueue_flush<double>(c, c.it, s);
+}
+
 // R = B - A X in FP64 with its partials (b.b, r.D^-1 r, r.r) in part[0..2].
+// Q is used as FP64 scratch (its float32 half is rewritten by the next SpMM).
 zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r) {
     zi_solver_ws *ws = c.ws;
     ZI_TILE_SWITCH(c.tile, launch_spmm, c.g, s, c.sys->sp_ptr, c.sys->sp_col,
                    (const double *)c.sys->sp_val, (const double *)ws->X, ws->Q, (double *)nullptr);
-    ZI_TILE_SWITCH(c.tile, launch_residual, c.g, s, c.sys, ws->dinv, ws->Q,
-                   write_r ? ws->R : (double *)nullptr, ws->part[0], ws->part[1], ws->part[2]);
+    ZI_TILE_SWITCH(c.tile, launch_residual, c.g, s, c.sys, (const int32_t *)c.colmap, ws->dinv,
+                   ws->Q, write_r ? ws->R : (double *)nullptr, ws->part[0], ws->part[1],
+                   ws->part[2]);
     ZI_HIP(hipGetLastError());
     return ZI_OK;
 }
 
+// P_it = D^-1 R (start or restart of the search directions).
 zi_status enqueue_restart_direction(SolveCtx &c, hipStream_t s) {
     if (c.mixed) {
+        float *p = c.P<float>(c.it);
         ZI_TILE_SWITCH(c.tile, launch_pupdate, c.g, s, (const double *)nullptr,
-                       (const double *)c.ws->dinv, (const double *)c.ws->R, c.P32());
+                       (const double *)c.ws->dinv, (const double *)c.ws->R, (const float *)p, p);
     } else {
+        double *p = c.P<double>(c.it);
         ZI_TILE_SWITCH(c.tile, launch_pupdate, c.g, s, (const double *)nullptr,
-                       (const double *)c.ws->dinv, (const double *)c.ws->R, c.ws->P);
+                       (const double *)c.ws->dinv, (const double *)c.ws->R, (const double *)p, p);
     }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
@@ -828,8 +1026,28 @@ int pick_tile(const zi_system *sys, int ldp, int precision, int requested) {
 // X = x0 or 0, R = B - A X, the per-column scalars and P = D^-1 R.
 zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipStream_t s) {
     c.t_start = std::chrono::steady_clock::now();
-    const int n = sys->n, L = sys->L;
+    const int n = sys->n;
+    const int L = o->columns ? o->n_columns : sys->L;
     const int ldp = L + (L & 1);
+    if (o->columns) {
+        if (o->n_columns < 1 || o->n_columns > sys->L) {
+            set_error("n_columns must be in [1, n_electrodes]");
+            return ZI_EINVAL;
+        }
+        std::vector<int32_t> map(sys->L, -1);
+        for (int k = 0; k < o->n_columns; ++k) {
+            const int l = o->columns[k];
+            if (l < 0 || l >= sys->L || map[l] >= 0) {
+                set_error("columns[%d] = %d out of range or repeated", k, l);
+                return ZI_EINVAL;
+            }
+            map[l] = k;
+        }
+        if (!sys->colmap) ZI_TRY(sys->pool.alloc(&sys->colmap, (size_t)sys->L));
+        ZI_HIP(hipMemcpyAsync(sys->colmap, map.data(), sizeof(int32_t) * sys->L,
+                              hipMemcpyHostToDevice, s));
+        c.colmap = sys->colmap;
+    }
     if (o->precond != ZI_PREC_JACOBI && o->precond != ZI_PREC_LDP) {
         set_error("unknown preconditioner %d", o->precond);
         return ZI_EINVAL;
@@ -859,9 +1077,11 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     c.ldp = ldp;
     c.L = L;
     c.maxit = o->maxit > 0 ? o->maxit : 50000;
-    c.check = o->check_every > 0 ? o->check_every : 8;
+    c.check = o->check_every > 0 ? o->check_every : (c.mixed ? MIXED_CHECK : 8);
+    c.check = ((c.check + LAZY - 1) / LAZY) * LAZY;   // chunks end on an X flush
     c.tol = o->tol > 0 ? o->tol : 1e-8;
     c.tol2 = c.tol * c.tol;
+    c.eta2 = 0.0;
     c.timing = o->timing != 0 && o->graph == 0;
     c.timer = EventTimer{&ws->ev};
     c.h_active.assign(ldp, 0);
@@ -871,6 +1091,7 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     sc.beta = ws->sc_d + 2 * ldp;
     sc.bb = ws->sc_d + 3 * ldp;
     sc.rr = ws->sc_d + 4 * ldp;
+    sc.tt = ws->sc_d + 5 * ldp;
     sc.iters = ws->sc_i;
     sc.active = ws->sc_i + ldp;
     sc.flag = ws->sc_i + 2 * ldp;
@@ -883,11 +1104,11 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
         ZI_TRY(copy_cols(o->x0, L, ws->X, ldp, n, L, s));
         ZI_TRY(true_residual(c, s, true));
     } else {
-        ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, ws->dinv, (const double *)nullptr,
-                       ws->R, ws->part[0], ws->part[1], ws->part[2]);
+        ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, (const int32_t *)c.colmap, ws->dinv,
+                       (const double *)nullptr, ws->R, ws->part[0], ws->part[1], ws->part[2]);
     }
     hipLaunchKernelGGL(k_red_init, dim3(ldp), dim3(RED), 0, s, sc, ws->part[0], ws->part[1],
-                       ws->part[2], c.g.nrt, L, c.tol2);
+                       ws->part[2], c.g.nrt, L, c.tol2, c.eta2);
     ZI_TRY(enqueue_restart_direction(c, s));
     ZI_TRY(read_active(c, s));
     c.done = !c.any_active;
@@ -902,9 +1123,10 @@ zi_status solve_after_converged(SolveCtx &c, hipStream_t s) {
         c.done = true;
         return ZI_OK;
     }
+    ZI_TRY(flush_all(c, s));
     ZI_TRY(true_residual(c, s, true));
     hipLaunchKernelGGL(k_red_refine, dim3(c.ldp), dim3(RED), 0, s, c.sc, c.ws->part[1],
-                       c.ws->part[2], c.g.nrt, c.L, c.tol2);
+                       c.ws->part[2], c.g.nrt, c.L, c.tol2, c.eta2);
     ZI_HIP(hipGetLastError());
     ZI_TRY(read_active(c, s));
     if (!c.any_active) {
@@ -929,6 +1151,10 @@ zi_status solve_check(SolveCtx &c, hipStream_t s) {
 zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
     zi_solver_ws *ws = c.ws;
     const int n = c.sys->n, L = c.L, ldp = c.ldp;
+    const bool timing = c.timing;
+    c.timing = false;
+    ZI_TRY(flush_all(c, s));
+    c.timing = timing;
     ZI_TRY(copy_cols(ws->X, ldp, T, L, n, L, s));
     std::vector<int32_t> h_iters(ldp);
     std::vector<double> h_rr(ldp), h_bb(ldp), h_true(ldp);
@@ -958,26 +1184,28 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
         st->tile = c.tile;
         st->n_kernels = 0;
         if (c.timing) {
-            double ms_spmm = 0, ms_upd = 0;
-            for (size_t k = 0; k + 1 < c.ev_spmm.size(); k += 2) {
-                float a = 0, b = 0;
-                ZI_HIP(hipEventElapsedTime(&a, c.ev_spmm[k], c.ev_spmm[k + 1]));
-                ZI_HIP(hipEventElapsedTime(&b, c.ev_upd[k], c.ev_upd[k + 1]));
-                ms_spmm += a;
-                ms_upd += b;
-            }
             const int64_t pe = c.mixed ? 4 : 8;   // bytes of a P or Q entry
             const int64_t ne = (int64_t)n * ldp;
             const int64_t abytes = (int64_t)c.sys->sp_nnz * (4 + pe) + (int64_t)(n + 1) * 4;
-            st->n_kernels = 2;
-            st->kernel_name[0] = "spmm_pq";
-            st->kernel_ms[0] = ms_spmm;
-            st->kernel_launches[0] = (int32_t)(c.ev_spmm.size() / 2);
-            st->kernel_bytes[0] = abytes + 2 * pe * ne;                 // read P, write Q
-            st->kernel_name[1] = "update";
-            st->kernel_ms[1] = ms_upd;
-            st->kernel_launches[1] = (int32_t)(c.ev_upd.size() / 2);
-            st->kernel_bytes[1] = (32 + 2 * pe) * ne + (int64_t)n * 8;  // r/w X, R; P, Q; D^-1
+            static const char *names[4] = {"spmm_pq", "update", "pupdate", "xflush"};
+            const int64_t bytes[4] = {
+                abytes + 2 * pe * ne,                      // read P, write Q
+                (16 + pe) * ne + (int64_t)n * 8,           // r/w R, read Q, D^-1
+                (8 + 2 * pe) * ne + (int64_t)n * 8,        // read R, P; write P; D^-1
+                (16 + LAZY * pe) * ne};                    // r/w X, read LAZY directions
+            st->n_kernels = 4;
+            for (int q = 0; q < 4; ++q) {
+                double ms = 0;
+                for (size_t k = 0; k + 1 < c.ev[q].size(); k += 2) {
+                    float a = 0;
+                    ZI_HIP(hipEventElapsedTime(&a, c.ev[q][k], c.ev[q][k + 1]));
+                    ms += a;
+                }
+                st->kernel_name[q] = names[q];
+                st->kernel_ms[q] = ms;
+                st->kernel_launches[q] = (int32_t)(c.ev[q].size() / 2);
+                st->kernel_bytes[q] = bytes[q];
+            }
         }
         st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - c.t_start).count();
     }
@@ -1011,7 +1239,9 @@ zi_status capture_graph(std::vector<SolveCtx *> &cs, std::vector<hipStream_t> &s
             st = ZI_EDEVICE;
             break;
         }
+        const int flushed = cs[k]->flushed;
         st = enqueue_iterations(*cs[k], count, streams[k]);
+        cs[k]->flushed = flushed;   // the replays, not the capture, advance it
         if (st == ZI_OK && hipEventRecord(joins[k], streams[k]) != hipSuccess) st = ZI_EDEVICE;
         if (st == ZI_OK && hipStreamWaitEvent(origin, joins[k], 0) != hipSuccess) st = ZI_EDEVICE;
     }
@@ -1051,7 +1281,14 @@ zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_so
         int exec_chunk = 0;
         zi_status r = ZI_OK;
         while (!c.done && r == ZI_OK) {
-            const int chunk = std::min(c.check, c.maxit - c.it);
+            const int chunk = c.check;
+            if (c.maxit - c.it < chunk) {   // the tail runs eagerly
+                r = enqueue_iterations(c, c.maxit - c.it, s);
+                if (r != ZI_OK) break;
+                c.it = c.maxit;
+                r = solve_check(c, s);
+                continue;
+            }
             if (!exec || chunk != exec_chunk) {
                 if (exec) (void)hipGraphExecDestroy(exec);
                 exec = nullptr;
@@ -1065,6 +1302,7 @@ zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_so
                 break;
             }
             c.it += chunk;
+            c.flushed = c.it;   // every chunk ends on an X flush (chunk % LAZY == 0)
             r = solve_check(c, s);
         }
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -1073,9 +1311,10 @@ zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_so
         ZI_TRY(r);
     } else {
         while (!c.done) {
-            ZI_TRY(enqueue_iterations(c, 1, s));
-            ++c.it;
-            if (c.it % c.check == 0 || c.it >= c.maxit) ZI_TRY(solve_check(c, s));
+            const int chunk = std::min(c.check, c.maxit - c.it);
+            ZI_TRY(enqueue_iterations(c, chunk, s));
+            c.it += chunk;
+            ZI_TRY(solve_check(c, s));
         }
     }
     return solve_end(c, T, st, s);
@@ -1097,7 +1336,7 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
             for (auto x : v) (void)hipStreamDestroy(x);
         }
     } guard{streams};
-    const int chunk = o->check_every > 0 ? o->check_every : 8;
+    const int chunk = cs[0].check;   // same options for every system
     hipGraphExec_t exec = nullptr;
     std::vector<int> members, last;
     zi_status r = ZI_OK;
@@ -1109,9 +1348,10 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
         for (int k = 0; k < nsys && r == ZI_OK; ++k) {
             if (cs[k].done || cs[k].maxit - cs[k].it >= chunk) continue;
             while (!cs[k].done && r == ZI_OK) {
-                r = enqueue_iterations(cs[k], 1, s);
-                ++cs[k].it;
-                if (r == ZI_OK && cs[k].it >= cs[k].maxit) r = solve_check(cs[k], s);
+                const int rest = cs[k].maxit - cs[k].it;
+                r = enqueue_iterations(cs[k], rest, s);
+                cs[k].it += rest;
+                if (r == ZI_OK) r = solve_check(cs[k], s);
             }
         }
         if (r != ZI_OK || members.empty()) break;
@@ -1135,6 +1375,7 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
         }
         for (int k : members) {
             cs[k].it += chunk;
+            cs[k].flushed = cs[k].it;
             r = solve_check(cs[k], s);
             if (r != ZI_OK) break;
         }
@@ -1168,9 +1409,10 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     ZI_TRY(fill_f64(ws->R, 1.0, (size_t)n * ldp, s));
     if (precision == ZI_FP32_SPMM_IR)
         hipLaunchKernelGGL(k_to_f32, dim3((unsigned)(((size_t)n * ldp + 255) / 256)), dim3(256), 0,
-                           s, ws->R, (int64_t)n * ldp, reinterpret_cast<float *>(ws->P));
+                           s, ws->R, (int64_t)n * ldp, reinterpret_cast<float *>(ws->P[0]));
     else
-        ZI_HIP(hipMemcpyAsync(ws->P, ws->R, sizeof(double) * n * ldp, hipMemcpyDeviceToDevice, s));
+        ZI_HIP(hipMemcpyAsync(ws->P[0], ws->R, sizeof(double) * n * ldp, hipMemcpyDeviceToDevice,
+                              s));
     ZI_HIP(hipGetLastError());
     hipEvent_t e0, e1;
     ZI_HIP(hipEventCreate(&e0));
@@ -1184,11 +1426,11 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
             ZI_HIP(hipEventRecord(e0, s));
             if (precision == ZI_FP32_SPMM_IR) {
                 ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
-                               (const float *)sys->sp_val32, (const float *)ws->P,
+                               (const float *)sys->sp_val32, (const float *)ws->P[0],
                                reinterpret_cast<float *>(ws->Q), ws->part[0]);
             } else {
                 ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
-                               (const double *)sys->sp_val, (const double *)ws->P, ws->Q,
+                               (const double *)sys->sp_val, (const double *)ws->P[0], ws->Q,
                                ws->part[0]);
             }
             ZI_HIP(hipEventRecord(e1, s));
@@ -1239,3 +1481,18 @@ zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double 
     (void)hipEventDestroy(e1);
     return ZI_OK;
 }
+
+namespace zi {
+
+// Y = A X for a float32 CSR matrix and n x ld float32 row-major blocks (ld
+// even), used by the warm-start network's graph aggregation.
+zi_status spmm_f32(const int32_t *rp, const int32_t *ci, const float *va, const float *X, float *Y,
+                   int32_t n, int32_t ld, hipStream_t s) {
+    const int tile = auto_tile(ld);
+    const Geom g = make_geom(n, ld, tile);
+    ZI_TILE_SWITCH(tile, launch_spmm, g, s, rp, ci, va, X, Y, (double *)nullptr);
+    ZI_HIP(hipGetLastError());
+    return ZI_OK;
+}
+
+}  // namespace zi

@@ -96,6 +96,13 @@ __global__ void k_copy_cols(const double *src, int32_t lds, double *dst, int32_t
     dst[r * ldd + c] = src[r * lds + c];
 }
 
+// Plain streaming copy with the 16-byte accesses of the solver kernels.
+__global__ void k_copy2(const double2 *src, double2 *dst, size_t n2) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 inline unsigned grid_for(size_t n, int threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
@@ -168,6 +175,24 @@ zi_status fill_f64(double *p, double value, size_t count, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(count, 256)), dim3(256), 0, s, p, value,
                        count);
     ZI_HIP(hipGetLastError());
+    return ZI_OK;
+}
+
+zi_status copy_probe(const double *src, double *dst, size_t n, double *ms, hipStream_t s) {
+    hipEvent_t e0, e1;
+    ZI_HIP(hipEventCreate(&e0));
+    ZI_HIP(hipEventCreate(&e1));
+    ZI_HIP(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(k_copy2, dim3(4096), dim3(256), 0, s, reinterpret_cast<const double2 *>(src),
+                       reinterpret_cast<double2 *>(dst), n / 2);
+    ZI_HIP(hipGetLastError());
+    ZI_HIP(hipEventRecord(e1, s));
+    ZI_HIP(hipEventSynchronize(e1));
+    float t = 0;
+    ZI_HIP(hipEventElapsedTime(&t, e0, e1));
+    if (ms) *ms = t;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return ZI_OK;
 }
 

@@ -116,8 +116,9 @@ zi_status zi_transfer_solve_batch(zi_system *const *systems, int32_t n_systems,
                 return ZI_EINVAL;
             }
     }
-    if (opts->tol < 0 || opts->maxit < 0 || opts->x0) {
-        set_error("tol and maxit must be non-negative; x0 is not supported in batches");
+    if (opts->tol < 0 || opts->maxit < 0 || opts->x0 || opts->columns) {
+        set_error("tol and maxit must be non-negative; x0 and columns are not supported in "
+                  "batches");
         return ZI_EINVAL;
     }
     ZI_GUARD(return zi_solve_batch_impl(systems, n_systems, opts, T, stats,
@@ -191,6 +192,84 @@ zi_status zi_eit_source(const zi_system *sys, const double *T, int32_t n_pattern
     }
     ZI_GUARD(return zi_eit_source_impl(sys, T, n_patterns, I, n_elems, elems, g_colptr, g_rowind,
                                        g_val, y_bg, (hipStream_t)hip_stream);)
+}
+
+zi_status zi_gnn_create(const zi_system *sys, int32_t n_layers, const int32_t *dims,
+                        zi_gnn **out) {
+    zi::g_err[0] = 0;
+    if (!sys || !dims || !out || n_layers < 1 || n_layers > 32) {
+        set_error("null argument or n_layers outside [1, 32]");
+        return ZI_EINVAL;
+    }
+    *out = nullptr;
+    for (int k = 0; k <= n_layers; ++k) {
+        if (dims[k] < 1 || dims[k] > 64 || (k < n_layers && dims[k] % 2 != 0)) {
+            set_error("dims[%d] = %d: need 1..64, even below the output layer", k, dims[k]);
+            return ZI_EINVAL;
+        }
+    }
+    ZI_GUARD(return zi_gnn_create_impl(sys, n_layers, dims, out);)
+}
+
+int64_t zi_gnn_param_count(const zi_gnn *net) { return net ? zi_gnn_param_count_impl(net) : 0; }
+
+zi_status zi_gnn_set_params(zi_gnn *net, const float *params) {
+    zi::g_err[0] = 0;
+    if (!net || !params) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_gnn_set_params_impl(net, params);)
+}
+
+zi_status zi_gnn_get_params(const zi_gnn *net, float *params) {
+    zi::g_err[0] = 0;
+    if (!net || !params) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_gnn_get_params_impl(net, params);)
+}
+
+zi_status zi_gnn_forward(zi_gnn *net, const float *X, float *y, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!net || !X || !y) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_gnn_forward_impl(net, X, y, (hipStream_t)hip_stream);)
+}
+
+zi_status zi_gnn_loss_grad(zi_gnn *net, const float *X, const float *t, double *loss,
+                           float *grads, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!net || !X || !t) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_gnn_loss_grad_impl(net, X, t, loss, grads, (hipStream_t)hip_stream);)
+}
+
+zi_status zi_gnn_adam_step(zi_gnn *net, float lr, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!net || !(lr > 0.f)) {
+        set_error("null argument or lr <= 0");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_gnn_adam_step_impl(net, lr, (hipStream_t)hip_stream);)
+}
+
+void zi_gnn_destroy(zi_gnn *net) {
+    if (net) zi_gnn_destroy_impl(net);
+}
+
+zi_status zi_copy_probe(const double *src, double *dst, int64_t n, double *ms, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!src || !dst || n < 2 || (n & 1)) {
+        set_error("null argument or n not a positive even count");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi::copy_probe(src, dst, (size_t)n, ms, (hipStream_t)hip_stream);)
 }
 
 int32_t zi_tile_count(void) { return zi_tile_count_impl(); }

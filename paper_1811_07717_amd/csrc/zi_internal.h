@@ -88,7 +88,10 @@ zi_status bucketize(const int32_t *keys, int32_t n_items, int32_t n_buckets,
                     int32_t *ptr, int32_t *items, bool sort, Pool &pool, hipStream_t s);
 
 zi_status fill_i32(int32_t *p, int32_t value, size_t count, hipStream_t s);
+zi_status spmm_f32(const int32_t *rp, const int32_t *ci, const float *va, const float *X, float *Y,
+                   int32_t n, int32_t ld, hipStream_t s);
 zi_status fill_f64(double *p, double value, size_t count, hipStream_t s);
+zi_status copy_probe(const double *src, double *dst, size_t n, double *ms, hipStream_t s);
 zi_status copy_cols(const double *src, int32_t lds, double *dst, int32_t ldd,
                     int32_t rows, int32_t cols, hipStream_t s);
 
@@ -136,6 +139,8 @@ struct zi_system {
     double *Pt = nullptr;        // n_cols x L (grows)
     size_t Pt_cap = 0;
 
+    int32_t *colmap = nullptr;   // electrode -> solved column for column subsets
+
     // SpMM tile chosen by zi_autotune per precision (for that ldp)
     int32_t tuned_tile[2] = {-1, -1};
     int32_t tuned_ldp[2] = {0, 0};
@@ -167,5 +172,14 @@ zi_status zi_eit_source_impl(const zi_system *sys, const double *T, int32_t P, c
                              int32_t ne, const int32_t *elems, int32_t *cp, int32_t *ri,
                              double *gv, double *y_bg, hipStream_t s);
 void zi_solver_ws_destroy(zi_solver_ws *ws);
+zi_status zi_gnn_create_impl(const zi_system *sys, int32_t K, const int32_t *dims, zi_gnn **out);
+void zi_gnn_destroy_impl(zi_gnn *g);
+int64_t zi_gnn_param_count_impl(const zi_gnn *g);
+zi_status zi_gnn_set_params_impl(zi_gnn *g, const float *p);
+zi_status zi_gnn_get_params_impl(const zi_gnn *g, float *p);
+zi_status zi_gnn_forward_impl(zi_gnn *g, const float *X, float *y, hipStream_t s);
+zi_status zi_gnn_loss_grad_impl(zi_gnn *g, const float *X, const float *t, double *loss,
+                                float *grads_host, hipStream_t s);
+zi_status zi_gnn_adam_step_impl(zi_gnn *g, float lr, hipStream_t s);
 int32_t zi_tile_count_impl();
 const char *zi_tile_name_impl(int32_t t);

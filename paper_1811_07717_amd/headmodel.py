@@ -303,3 +303,24 @@ def batch_heads(count=64, seed=1815, h_range=(2.5, 6.0), Ls=(32, 64, 96, 128), m
         L = int(rng.choice(Ls))
         heads.append(make_head(h, L=L, m=m, seed=seed + 1 + k, sigmas=sig, scale=scale))
     return heads
+
+
+def perturbed_sigma(H, seed, sd=0.2, smooth_mm=8.0):
+    """Per-tet conductivity with a smooth log-normal perturbation.
+
+    White noise on the cube grid, smoothed with a Gaussian kernel of
+    ``smooth_mm`` (standard deviation), re-standardised to ``sd`` over the
+    tetrahedra and applied as sigma * exp(noise).  A tet takes the value of its
+    cube (the cube of its first, minimum-corner vertex).
+    """
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    h = H.h_mm * 1e-3
+    corner = np.rint(H.nodes[H.tets[:, 0]] / h).astype(np.int64)
+    lo = corner.min(axis=0)
+    idx = corner - lo
+    shape = tuple(idx.max(axis=0) + 1)
+    field = gaussian_filter(rng.standard_normal(shape), sigma=smooth_mm / H.h_mm, mode="wrap")
+    v = field[idx[:, 0], idx[:, 1], idx[:, 2]]
+    v = (v - v.mean()) / v.std() * sd
+    return H.sigma * np.exp(v)

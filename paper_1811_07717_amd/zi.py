@@ -41,7 +41,8 @@ class ZiSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("graph", ctypes.c_int32), ("x0", ctypes.c_void_p)]
+                ("tile", ctypes.c_int32), ("graph", ctypes.c_int32), ("x0", ctypes.c_void_p),
+                ("columns", c_i32p), ("n_columns", ctypes.c_int32)]
 
 
 class ZiSolveStats(ctypes.Structure):
@@ -91,6 +92,19 @@ SIGNATURES = [
                                      ctypes.c_void_p, ctypes.c_void_p, c_f64p, ctypes.c_void_p]),
     ("zi_spmm", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_int32, c_f64p, ctypes.c_void_p]),
+    ("zi_gnn_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, c_i32p,
+                                     ctypes.POINTER(ctypes.c_void_p)]),
+    ("zi_gnn_param_count", ctypes.c_int64, [ctypes.c_void_p]),
+    ("zi_gnn_set_params", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("zi_gnn_get_params", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("zi_gnn_forward", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    ("zi_gnn_loss_grad", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        c_f64p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("zi_gnn_adam_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
+    ("zi_gnn_destroy", None, [ctypes.c_void_p]),
+    ("zi_copy_probe", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, c_f64p,
+                                     ctypes.c_void_p]),
     ("zi_tile_count", ctypes.c_int32, []),
     ("zi_tile_name", ctypes.c_char_p, [ctypes.c_int32]),
     ("zi_get_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ZiInfo)]),
@@ -229,20 +243,25 @@ class System:
     # -- solve ---------------------------------------------------------------
     def transfer_solve(self, tol=1e-8, maxit=0, precond="jacobi", precision="fp64",
                        check_every=0, timing=False, tile=-1, x0=None, out=None,
-                       raise_on_error=True, graph=False):
+                       raise_on_error=True, graph=False, columns=None):
         import torch
-        T = out if out is not None else torch.empty((self.n, self.L), dtype=torch.float64,
+        cols = None if columns is None else np.ascontiguousarray(np.asarray(columns,
+                                                                            dtype=np.int32))
+        nc = self.L if cols is None else int(cols.shape[0])
+        T = out if out is not None else torch.empty((self.n, nc), dtype=torch.float64,
                                                      device="cuda")
-        iters = np.zeros(self.L, dtype=np.int32)
-        rec = np.zeros(self.L)
-        true = np.zeros(self.L)
+        iters = np.zeros(nc, dtype=np.int32)
+        rec = np.zeros(nc)
+        true = np.zeros(nc)
         st = ZiSolveStats()
         st.iters = iters.ctypes.data_as(c_i32p)
         st.relres_rec = rec.ctypes.data_as(c_f64p)
         st.relres_true = true.ctypes.data_as(c_f64p)
         o = ZiSolveOpts(float(tol), int(maxit), PRECOND[precond], PRECISION[precision],
                         int(check_every), int(bool(timing)), int(tile), int(bool(graph)),
-                        _dev(x0, torch.float64, "x0") if x0 is not None else None)
+                        _dev(x0, torch.float64, "x0") if x0 is not None else None,
+                        cols.ctypes.data_as(c_i32p) if cols is not None else None,
+                        nc if cols is not None else 0)
         rc = lib().zi_transfer_solve(self._h, ctypes.byref(o), _dev(T, torch.float64, "T"),
                                      ctypes.byref(st), _stream())
         stats = dict(iters=iters, relres_rec=rec, relres_true=true, seconds=st.seconds,
@@ -321,6 +340,15 @@ class System:
         return Y, ms.value
 
 
+def copy_probe(src, dst):
+    """Time the library's 16-byte streaming copy of src into dst (float64)."""
+    import torch
+    ms = ctypes.c_double(0.0)
+    _check(lib().zi_copy_probe(_dev(src, torch.float64, "src"), _dev(dst, torch.float64, "dst"),
+                               int(src.numel()), ctypes.byref(ms), _stream()), "zi_copy_probe")
+    return ms.value
+
+
 def tile_names():
     return [lib().zi_tile_name(t).decode() for t in range(lib().zi_tile_count())]
 
@@ -344,7 +372,7 @@ def transfer_solve_batch(systems, tol=1e-8, maxit=0, precond="jacobi", precision
         sts[j].relres_rec = rec.ctypes.data_as(c_f64p)
         sts[j].relres_true = tr.ctypes.data_as(c_f64p)
     o = ZiSolveOpts(float(tol), int(maxit), PRECOND[precond], PRECISION[precision],
-                    int(check_every), 0, int(tile), 1, None)
+                    int(check_every), 0, int(tile), 1, None, None, 0)
     rc = lib().zi_transfer_solve_batch(hs, k, ctypes.byref(o), tp, sts, _stream())
     if raise_on_error:
         _check(rc, "zi_transfer_solve_batch")
@@ -352,3 +380,58 @@ def transfer_solve_batch(systems, tol=1e-8, maxit=0, precond="jacobi", precision
                   refinements=sts[j].refinements, tile=sts[j].tile, seconds=sts[j].seconds)
              for j, (it, rec, tr) in enumerate(keep)]
     return Ts, stats, rc
+
+
+class MeshGNN:
+    """zi_gnn: the warm-start mesh-graph network on a system's mesh graph."""
+
+    def __init__(self, system, dims):
+        self._sys = system
+        self.dims = [int(d) for d in dims]
+        d = np.asarray(self.dims, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().zi_gnn_create(system._h, len(dims) - 1, d.ctypes.data_as(c_i32p),
+                                   ctypes.byref(h)), "zi_gnn_create")
+        self._h = h
+        self.n_params = int(lib().zi_gnn_param_count(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().zi_gnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        f = np.ascontiguousarray(np.asarray(flat, dtype=np.float32))
+        assert f.shape == (self.n_params,)
+        _check(lib().zi_gnn_set_params(self._h, f.ctypes.data), "zi_gnn_set_params")
+
+    def get_params(self):
+        f = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().zi_gnn_get_params(self._h, f.ctypes.data), "zi_gnn_get_params")
+        return f
+
+    def forward(self, X):
+        import torch
+        y = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().zi_gnn_forward(self._h, _dev(X, torch.float32, "X"),
+                                    _dev(y, torch.float32, "y"), _stream()), "zi_gnn_forward")
+        return y
+
+    def loss_grad(self, X, t, want_grads=False):
+        import torch
+        loss = ctypes.c_double(0.0)
+        g = np.zeros(self.n_params, dtype=np.float32) if want_grads else None
+        _check(lib().zi_gnn_loss_grad(self._h, _dev(X, torch.float32, "X"),
+                                      _dev(t, torch.float32, "t"), ctypes.byref(loss),
+                                      g.ctypes.data if g is not None else None, _stream()),
+               "zi_gnn_loss_grad")
+        return loss.value, g
+
+    def adam_step(self, lr):
+        _check(lib().zi_gnn_adam_step(self._h, float(lr), _stream()), "zi_gnn_adam_step")

@@ -84,5 +84,11 @@ def test_autotuner_picks_a_tile_and_results_do_not_change():
     assert 0 <= best < len(ms) and ms[best] == ms.min() and np.all(ms > 0)
     T1, s1 = g.transfer_solve(tol=1e-8)
     assert s1["tile"] == best
-    assert torch.equal(T0, T1)      # every tile sums in the same order
+    # The products are bit-identical across tiles, but the dot-product partial
+    # sums follow the tile's row blocking, so the iterates differ by rounding.
+    assert np.abs(s1["iters"] - s0["iters"]).max() <= 2
+    err = (T0 - T1).norm(dim=0) / T0.norm(dim=0)
+    assert err.max().item() <= 1e-6
+    T2, _ = g.transfer_solve(tol=1e-8)
+    assert torch.equal(T1, T2)      # deterministic for a given tile
     g.close()
