@@ -42,8 +42,8 @@ def parse():
                    help="also time zi_spmm with every tile on an n x L block")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="also run one torch copy of this many MiB (counter calibration)")
-    p.add_argument("--autotune", action="store_true",
-                   help="run zi_autotune on the workload before timing")
+    p.add_argument("--no-autotune", dest="autotune", action="store_false",
+                   help="skip zi_autotune (default: tune the SpMM tile once before timing)")
     return p.parse_args()
 
 

@@ -14,6 +14,7 @@
 //   7. CEM: triangle areas, contact areas, surface mass into A, B node-major
 //      and electrode-major, all in fixed orders;
 //   8. ground node (smallest admissible) and the symmetric ground fix.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -466,27 +467,143 @@ __device__ __forceinline__ bool keep_entry(int64_t i, int32_t j, double v, const
     return fabs(v) > DROP * sqrt(fabs(diag[i] * diag[j]));
 }
 
-__global__ void k_nz_count(const int32_t *row_ptr, const int32_t *col, const double *val,
-                           const double *diag, int32_t n, int32_t *len) {
+// ---------------------------------------------------------------------------
+// solver row order
+// ---------------------------------------------------------------------------
+// Every PCG iteration multiplies A by an n x L block whose rows are ~L*8 bytes;
+// a row's product gathers the rows of its mesh neighbours.  In the order the
+// caller numbers the nodes (lexicographic on a grid) neighbours lie a whole
+// grid plane apart, far more rows than one XCD's L2 holds, so each row of the
+// block is fetched from memory about three times per product.  The solver
+// therefore renumbers the nodes: the bounding box is cut into cubic cells of
+// about one node spacing, the cells into pencils of PENCIL x PENCIL cells
+// along z, the pencils are visited in a snake order (and z alternates
+// direction from pencil to pencil), and inside a pencil the nodes go by z,
+// then y, then x.  Mesh neighbours are then at most a pencil layer (a few
+// hundred rows) apart.  Nodes sharing a cell keep their relative order, so
+// the permutation is deterministic.
+constexpr int PENCIL = 8;
+
+struct CellGrid {
+    double lo[3], h;
+    int nc[3];          // cells per axis
+    int np[2];          // pencils along x and y
+};
+
+__global__ void k_bbox_part(const double *nodes, int32_t n, double *part) {
+    __shared__ double s[6][256];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int k = 0; k < 3; ++k) {
+            const double x = nodes[3 * i + k];
+            v[k] = fmin(v[k], x);
+            v[3 + k] = fmax(v[3 + k], x);
+        }
+    }
+    for (int k = 0; k < 6; ++k) s[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            for (int k = 0; k < 3; ++k) {
+                s[k][threadIdx.x] = fmin(s[k][threadIdx.x], s[k][threadIdx.x + off]);
+                s[3 + k][threadIdx.x] = fmax(s[3 + k][threadIdx.x], s[3 + k][threadIdx.x + off]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__device__ __forceinline__ int cell_of(double x, double lo, double h, int nc) {
+    const double t = (x - lo) / h;
+    if (!(t > 0.0)) return 0;
+    return t >= (double)(nc - 1) ? nc - 1 : (int)t;
+}
+
+__global__ void k_cell_key(const double *nodes, int32_t n, CellGrid g, int32_t *key) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int cx = cell_of(nodes[3 * i + 0], g.lo[0], g.h, g.nc[0]);
+    const int cy = cell_of(nodes[3 * i + 1], g.lo[1], g.h, g.nc[1]);
+    int cz = cell_of(nodes[3 * i + 2], g.lo[2], g.h, g.nc[2]);
+    const int px = cx / PENCIL, py = cy / PENCIL;
+    const int pid = py * g.np[0] + ((py & 1) ? g.np[0] - 1 - px : px);
+    if (pid & 1) cz = g.nc[2] - 1 - cz;
+    key[i] = ((pid * g.nc[2] + cz) * PENCIL + cy % PENCIL) * PENCIL + cx % PENCIL;
+}
+
+__global__ void k_inverse_perm(const int32_t *perm, int32_t n, int32_t *iperm) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) iperm[perm[r]] = (int32_t)r;
+}
+
+// Cell grid for n nodes in the box [lo, hi]: cells of the edge length that
+// gives about one node per cell of the box, enlarged where the key space
+// would exceed 4 n + 4096 buckets (flat or strongly graded meshes).
+CellGrid make_cell_grid(const double lo[3], const double hi[3], int32_t n, int64_t *buckets) {
+    CellGrid g{};
+    double ext[3], emax = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        g.lo[k] = lo[k];
+        ext[k] = hi[k] > lo[k] ? hi[k] - lo[k] : 0.0;
+        emax = std::max(emax, ext[k]);
+    }
+    const double floor_ext = emax > 0.0 ? 1e-6 * emax : 1.0;
+    double vol = 1.0;
+    for (int k = 0; k < 3; ++k) vol *= std::max(ext[k], floor_ext);
+    g.h = std::cbrt(vol / std::max(n, 1));
+    if (!(g.h > 0.0) || !std::isfinite(g.h)) g.h = 1.0;
+    const int64_t cap = 4 * (int64_t)n + 4096;
+    for (;;) {
+        int64_t nc[3];
+        for (int k = 0; k < 3; ++k)
+            nc[k] = std::max<int64_t>(1, (int64_t)std::ceil(ext[k] / g.h));
+        const int64_t npx = (nc[0] + PENCIL - 1) / PENCIL, npy = (nc[1] + PENCIL - 1) / PENCIL;
+        const int64_t total = npx * npy * nc[2] * PENCIL * PENCIL;
+        if (total <= cap) {
+            for (int k = 0; k < 3; ++k) g.nc[k] = (int)nc[k];
+            g.np[0] = (int)npx;
+            g.np[1] = (int)npy;
+            *buckets = total;
+            return g;
+        }
+        g.h *= 1.26;
+    }
+}
+
+// Solver copy of row perm[r], renumbered through iperm, columns ascending.
+__global__ void k_nz_count(const int32_t *row_ptr, const int32_t *col, const double *val,
+                           const double *diag, const int32_t *perm, int32_t n, int32_t *len) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t i = perm[r];
     int cnt = 0;
     for (int32_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) cnt += keep_entry(i, col[q], val[q], diag);
-    len[i] = cnt;
+    len[r] = cnt;
 }
 
 __global__ void k_nz_fill(const int32_t *row_ptr, const int32_t *col, const double *val,
-                          const double *diag, int32_t n, const int32_t *sp_ptr, int32_t *sp_col,
-                          double *sp_val) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t o = sp_ptr[i];
+                          const double *diag, const int32_t *perm, const int32_t *iperm,
+                          int32_t n, const int32_t *sp_ptr, int32_t *sp_col, double *sp_val) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t i = perm[r];
+    const int32_t s = sp_ptr[r];
+    int32_t o = s;
     for (int32_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
-        if (keep_entry(i, col[q], val[q], diag)) {
-            sp_col[o] = col[q];
-            sp_val[o] = val[q];
-            ++o;
+        if (!keep_entry(i, col[q], val[q], diag)) continue;
+        const int32_t c = iperm[col[q]];
+        const double v = val[q];
+        int32_t j = o - 1;
+        while (j >= s && sp_col[j] > c) {
+            sp_col[j + 1] = sp_col[j];
+            sp_val[j + 1] = sp_val[j];
+            --j;
         }
+        sp_col[j + 1] = c;
+        sp_val[j + 1] = v;
+        ++o;
     }
 }
 
@@ -806,11 +923,41 @@ zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t
     hipLaunchKernelGGL(k_diags, dim3(grid_for(n, 256)), dim3(256), 0, s, sys->row_ptr, sys->col,
                        sys->val, n, sys->diag, sys->absrow);
     ZI_HIP(hipGetLastError());
+    {   // solver row order
+        constexpr int NBB = 256;
+        double *bb = nullptr;
+        ZI_TRY(tmp.alloc(&bb, (size_t)NBB * 6));
+        hipLaunchKernelGGL(k_bbox_part, dim3(NBB), dim3(256), 0, s, sys->nodes, n, bb);
+        ZI_HIP(hipGetLastError());
+        std::vector<double> hb((size_t)NBB * 6);
+        ZI_HIP(hipMemcpyAsync(hb.data(), bb, sizeof(double) * NBB * 6, hipMemcpyDeviceToHost, s));
+        ZI_HIP(hipStreamSynchronize(s));
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int b = 0; b < NBB; ++b)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], hb[b * 6 + k]);
+                hi[k] = std::max(hi[k], hb[b * 6 + 3 + k]);
+            }
+        int64_t nbk = 0;
+        const CellGrid cg = make_cell_grid(lo, hi, n, &nbk);
+        int32_t *key = nullptr, *kptr = nullptr;
+        ZI_TRY(tmp.alloc(&key, (size_t)n));
+        ZI_TRY(tmp.alloc(&kptr, (size_t)nbk + 1));
+        ZI_TRY(P.alloc(&sys->perm, (size_t)n));
+        ZI_TRY(P.alloc(&sys->iperm, (size_t)n));
+        hipLaunchKernelGGL(k_cell_key, dim3(grid_for(n, 256)), dim3(256), 0, s, sys->nodes, n, cg,
+                           key);
+        ZI_HIP(hipGetLastError());
+        ZI_TRY(bucketize(key, n, (int32_t)nbk, kptr, sys->perm, true, tmp, s));
+        hipLaunchKernelGGL(k_inverse_perm, dim3(grid_for(n, 256)), dim3(256), 0, s, sys->perm, n,
+                           sys->iperm);
+        ZI_HIP(hipGetLastError());
+    }
     int32_t *splen = nullptr;
     ZI_TRY(tmp.alloc(&splen, (size_t)n));
     ZI_TRY(P.alloc(&sys->sp_ptr, (size_t)n + 1));
     hipLaunchKernelGGL(k_nz_count, dim3(grid_for(n, 256)), dim3(256), 0, s, sys->row_ptr, sys->col,
-                       sys->val, sys->diag, n, splen);
+                       sys->val, sys->diag, sys->perm, n, splen);
     ZI_HIP(hipGetLastError());
     ZI_TRY(scan_exclusive(splen, sys->sp_ptr, n, tmp, s));
     int32_t spnnz = 0;
@@ -820,7 +967,8 @@ zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t
     ZI_TRY(P.alloc(&sys->sp_col, (size_t)spnnz));
     ZI_TRY(P.alloc(&sys->sp_val, (size_t)spnnz));
     hipLaunchKernelGGL(k_nz_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, sys->row_ptr, sys->col,
-                       sys->val, sys->diag, n, sys->sp_ptr, sys->sp_col, sys->sp_val);
+                       sys->val, sys->diag, sys->perm, sys->iperm, n, sys->sp_ptr, sys->sp_col,
+                       sys->sp_val);
     ZI_HIP(hipGetLastError());
     ZI_HIP(hipStreamSynchronize(s));
     tmp.release();

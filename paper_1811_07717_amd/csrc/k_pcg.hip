@@ -441,9 +441,11 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
 }
 
 // R = B - Q (Q may be null: R = B).  Partials: b.b, r.D^-1 r, r.r.  R may be
-// null (only the partials are wanted: true residual).
+// null (only the partials are wanted: true residual).  Solver row r takes the
+// right-hand side of node perm[r].
 template <int LPR, int NV>
-__global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__restrict__ bp,
+__global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__restrict__ perm,
+                                                    const int32_t *__restrict__ bp,
                                                     const int32_t *__restrict__ bc,
                                                     const double *__restrict__ bv,
                                                     const int32_t *__restrict__ colmap,
@@ -461,7 +463,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__res
         const int row = base + ln.slot;
         if (row >= sc.re) continue;
         const double di = dinv[row];
-        const int s = bp[row], e = bp[row + 1];
+        const int node = perm[row];
+        const int s = bp[node], e = bp[node + 1];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (!ln.ok[v]) continue;
@@ -643,19 +646,24 @@ constexpr int NTILES = sizeof(kTiles) / sizeof(kTiles[0]);
         default: FN<64, 4>(__VA_ARGS__); break;             \
     }
 
+// Default tile without autotuning: the cooperative-front schedule with the
+// narrowest column chunk that holds every column, two column pairs per lane
+// where that chunk width allows it (measured fastest on the 2 mm sphere for
+// 64-256 columns); below 16 columns the chunk-schedule lpr4 tile.
 int auto_tile(int ldp) {
-    // narrowest single chunk (chunk schedule) that holds every column, else
-    // the widest tile
-    int best = -1, bestcw = 1 << 30;
+    int best = -1, bestcw = 1 << 30, bestnv = 0;
     for (int t = 0; t < NTILES; ++t) {
-        if (kTiles[t].front) continue;
+        if (!kTiles[t].front) continue;
         const int cw = 2 * kTiles[t].lpr * kTiles[t].nv;
-        if (cw >= ldp && cw < bestcw) {
+        if (cw < ldp) continue;
+        if (cw < bestcw || (cw == bestcw && kTiles[t].nv > bestnv)) {
             best = t;
             bestcw = cw;
+            bestnv = kTiles[t].nv;
         }
     }
-    return best >= 0 ? best : 9;
+    if (ldp <= 8) return 8;           // lpr4_nv1_cw8
+    return best >= 0 ? best : 9;      // wider than any front tile: lpr64_nv4_cw512
 }
 
 Geom make_geom(int n, int ldp, int tile) {
@@ -729,8 +737,8 @@ template <int LPR, int NV>
 void launch_residual(const Geom &g, hipStream_t s, const zi_system *sys, const int32_t *colmap,
                      const double *dinv, const double *Q, double *R, double *pbb, double *prz,
                      double *prr) {
-    hipLaunchKernelGGL((k_residual<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, sys->b_ptr,
-                       sys->b_col, sys->b_val, colmap, dinv, Q, R, pbb, prz, prr);
+    hipLaunchKernelGGL((k_residual<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, sys->perm,
+                       sys->b_ptr, sys->b_col, sys->b_val, colmap, dinv, Q, R, pbb, prz, prr);
 }
 
 __global__ void k_to_f32(const double *a, int64_t n, float *b) {
@@ -738,9 +746,10 @@ __global__ void k_to_f32(const double *a, int64_t n, float *b) {
     if (i < n) b[i] = (float)a[i];
 }
 
-__global__ void k_dinv(const double *d, int32_t n, double *dinv) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dinv[i] = 1.0 / d[i];
+// Preconditioner in solver row order: dinv[r] = 1 / d[perm[r]].
+__global__ void k_dinv(const double *d, const int32_t *perm, int32_t n, double *dinv) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) dinv[r] = 1.0 / d[perm[r]];
 }
 
 }  // namespace
@@ -1097,11 +1106,12 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     sc.flag = ws->sc_i + 2 * ldp;
 
     hipLaunchKernelGGL(k_dinv, dim3((n + 255) / 256), dim3(256), 0, s,
-                       o->precond == ZI_PREC_LDP ? sys->absrow : sys->diag, n, ws->dinv);
+                       o->precond == ZI_PREC_LDP ? sys->absrow : sys->diag, sys->perm, n,
+                       ws->dinv);
     ZI_TRY(fill_i32(sc.flag, 0, 1, s));
     ZI_TRY(fill_f64(ws->X, 0.0, (size_t)n * ldp, s));
     if (o->x0) {
-        ZI_TRY(copy_cols(o->x0, L, ws->X, ldp, n, L, s));
+        ZI_TRY(gather_rows(o->x0, L, sys->perm, ws->X, ldp, n, L, s));
         ZI_TRY(true_residual(c, s, true));
     } else {
         ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, (const int32_t *)c.colmap, ws->dinv,
@@ -1155,7 +1165,7 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
     c.timing = false;
     ZI_TRY(flush_all(c, s));
     c.timing = timing;
-    ZI_TRY(copy_cols(ws->X, ldp, T, L, n, L, s));
+    ZI_TRY(gather_rows(ws->X, ldp, c.sys->iperm, T, L, n, L, s));
     std::vector<int32_t> h_iters(ldp);
     std::vector<double> h_rr(ldp), h_bb(ldp), h_true(ldp);
     ZI_HIP(hipMemcpyAsync(h_iters.data(), c.sc.iters, sizeof(int32_t) * ldp, hipMemcpyDeviceToHost, s));
@@ -1464,16 +1474,23 @@ zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double 
         set_error("tile %d out of range", tile);
         return ZI_EINVAL;
     }
-    const Geom g = make_geom(sys->n, k, tile);
+    const int n = sys->n;
+    const Geom g = make_geom(n, k, tile);
+    Pool tmp;   // the blocks in solver row order
+    double *Xp = nullptr, *Yp = nullptr;
+    ZI_TRY(tmp.alloc(&Xp, (size_t)n * k));
+    ZI_TRY(tmp.alloc(&Yp, (size_t)n * k));
+    ZI_TRY(gather_rows(X, k, sys->perm, Xp, k, n, k, s));
     hipEvent_t e0, e1;
     ZI_HIP(hipEventCreate(&e0));
     ZI_HIP(hipEventCreate(&e1));
     ZI_HIP(hipEventRecord(e0, s));
     ZI_TILE_SWITCH(tile, launch_spmm, g, s, sys->sp_ptr, sys->sp_col, (const double *)sys->sp_val,
-                   X, Y, (double *)nullptr);
+                   (const double *)Xp, Yp, (double *)nullptr);
     ZI_HIP(hipGetLastError());
     ZI_HIP(hipEventRecord(e1, s));
-    ZI_HIP(hipEventSynchronize(e1));
+    ZI_TRY(gather_rows(Yp, k, sys->iperm, Y, k, n, k, s));
+    ZI_HIP(hipStreamSynchronize(s));
     float t = 0;
     ZI_HIP(hipEventElapsedTime(&t, e0, e1));
     if (ms) *ms = t;

@@ -96,6 +96,14 @@ __global__ void k_copy_cols(const double *src, int32_t lds, double *dst, int32_t
     dst[r * ldd + c] = src[r * lds + c];
 }
 
+__global__ void k_gather_rows(const double *src, int32_t lds, const int32_t *rows, double *dst,
+                              int32_t ldd, int32_t n, int32_t cols) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)n * cols) return;
+    const size_t r = i / cols, c = i % cols;
+    dst[r * ldd + c] = src[(size_t)rows[r] * lds + c];
+}
+
 // Plain streaming copy with the 16-byte accesses of the solver kernels.
 __global__ void k_copy2(const double2 *src, double2 *dst, size_t n2) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
@@ -202,6 +210,16 @@ zi_status copy_cols(const double *src, int32_t lds, double *dst, int32_t ldd, in
     if (total == 0) return ZI_OK;
     hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(total, 256)), dim3(256), 0, s, src, lds, dst,
                        ldd, rows, cols);
+    ZI_HIP(hipGetLastError());
+    return ZI_OK;
+}
+
+zi_status gather_rows(const double *src, int32_t lds, const int32_t *rows, double *dst,
+                      int32_t ldd, int32_t n, int32_t cols, hipStream_t s) {
+    const size_t total = (size_t)n * cols;
+    if (total == 0) return ZI_OK;
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(total, 256)), dim3(256), 0, s, src, lds, rows,
+                       dst, ldd, n, cols);
     ZI_HIP(hipGetLastError());
     return ZI_OK;
 }

@@ -94,6 +94,9 @@ zi_status fill_f64(double *p, double value, size_t count, hipStream_t s);
 zi_status copy_probe(const double *src, double *dst, size_t n, double *ms, hipStream_t s);
 zi_status copy_cols(const double *src, int32_t lds, double *dst, int32_t ldd,
                     int32_t rows, int32_t cols, hipStream_t s);
+// dst[r * ldd + c] = src[rows[r] * lds + c] for r < n, c < cols.
+zi_status gather_rows(const double *src, int32_t lds, const int32_t *rows, double *dst,
+                      int32_t ldd, int32_t n, int32_t cols, hipStream_t s);
 
 }  // namespace zi
 
@@ -119,7 +122,10 @@ struct zi_system {
     int32_t *row_ptr = nullptr, *col = nullptr;
     double *val = nullptr;
     // the solver's copy of A: off-diagonal entries below 64 eps sqrt(a_ii a_jj)
-    // (rounding residue of couplings that vanish in exact arithmetic) left out
+    // (rounding residue of couplings that vanish in exact arithmetic) left out,
+    // rows and columns in the solver's locality order: solver row r is node
+    // perm[r], node i is solver row iperm[i]
+    int32_t *perm = nullptr, *iperm = nullptr;
     int32_t *sp_ptr = nullptr, *sp_col = nullptr;
     double *sp_val = nullptr;
     float *sp_val32 = nullptr;   // float32 copy for the mixed-precision solve
