@@ -127,6 +127,26 @@ __device__ __forceinline__ void st2(double *p, double2 v) {
 __device__ __forceinline__ void st2(float *p, double2 v) {
     *reinterpret_cast<float2 *>(p) = make_float2((float)v.x, (float)v.y);
 }
+// Streaming (nontemporal) pair accesses for block vectors that a kernel
+// touches once: each block vector is far larger than L2 and the Infinity
+// Cache, and keeping it out of them leaves room for the SpMM's gathers.  Two
+// adjacent scalar accesses become one 16-byte (8-byte) memory instruction.
+__device__ __forceinline__ double2 ldn2(const double *p) {
+    return make_double2(__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1));
+}
+__device__ __forceinline__ double2 ldn2(const float *p) {
+    return make_double2((double)__builtin_nontemporal_load(p),
+                        (double)__builtin_nontemporal_load(p + 1));
+}
+__device__ __forceinline__ void stn2(double *p, double2 v) {
+    __builtin_nontemporal_store(v.x, p);
+    __builtin_nontemporal_store(v.y, p + 1);
+}
+__device__ __forceinline__ void stn2(float *p, double2 v) {
+    __builtin_nontemporal_store((float)v.x, p);
+    __builtin_nontemporal_store((float)v.y, p + 1);
+}
+
 template <class T>
 struct Pair;
 template <>
@@ -135,6 +155,7 @@ struct Pair<double> {
     __device__ static double2 zero() { return make_double2(0.0, 0.0); }
     __device__ static double2 load(const double *p) { return *reinterpret_cast<const double2 *>(p); }
     __device__ static void store(double *p, double2 v) { *reinterpret_cast<double2 *>(p) = v; }
+    __device__ static void store_nt(double *p, double2 v) { stn2(p, v); }
     __device__ static double2 widen(double2 v) { return v; }
 };
 template <>
@@ -143,6 +164,10 @@ struct Pair<float> {
     __device__ static float2 zero() { return make_float2(0.f, 0.f); }
     __device__ static float2 load(const float *p) { return *reinterpret_cast<const float2 *>(p); }
     __device__ static void store(float *p, float2 v) { *reinterpret_cast<float2 *>(p) = v; }
+    __device__ static void store_nt(float *p, float2 v) {
+        __builtin_nontemporal_store(v.x, p);
+        __builtin_nontemporal_store(v.y, p + 1);
+    }
     __device__ static double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
 };
 
@@ -195,8 +220,8 @@ __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
         int jv = row;
         T av = T(0);
         if (lr < BATCH && lr < cnt) {
-            jv = ci[kb + lr];
-            av = va[kb + lr];
+            jv = __builtin_nontemporal_load(ci + kb + lr);
+            av = __builtin_nontemporal_load(va + kb + lr);
         }
         typename PT::type x[BATCH][NV];
 #pragma unroll
@@ -273,7 +298,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (!ln.ok[v]) continue;
-            PT::store(Y + (size_t)row * g.ldp + ln.c[v], acc[v]);
+            PT::store_nt(Y + (size_t)row * g.ldp + ln.c[v], acc[v]);
             if (WITH_DOT) {
                 const double2 p = PT::widen(PT::load(X + (size_t)row * g.ldp + ln.c[v]));
                 const double2 q = PT::widen(acc[v]);
@@ -321,8 +346,8 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
             for (int v = 0; v < NV; ++v) {
                 const size_t o = (size_t)row * g.ldp + ln.c[v];
                 const bool on = rv && ln.ok[v];
-                r[u][v] = on ? ld2(R + o) : make_double2(0.0, 0.0);
-                q[u][v] = on ? ld2(Q + o) : make_double2(0.0, 0.0);
+                r[u][v] = on ? ldn2(R + o) : make_double2(0.0, 0.0);
+                q[u][v] = on ? ldn2(Q + o) : make_double2(0.0, 0.0);
             }
         }
 #pragma unroll
@@ -334,7 +359,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
                 double2 rr = r[u][v];
                 rr.x = fma(-al[v].x, q[u][v].x, rr.x);
                 rr.y = fma(-al[v].y, q[u][v].y, rr.y);
-                st2(R + (size_t)row * g.ldp + ln.c[v], rr);
+                stn2(R + (size_t)row * g.ldp + ln.c[v], rr);
                 acc[0][v].x = fma(rr.x, rr.x * di[u], acc[0][v].x);
                 acc[0][v].y = fma(rr.y, rr.y * di[u], acc[0][v].y);
                 acc[1][v].x = fma(rr.x, rr.x, acc[1][v].x);
@@ -376,8 +401,8 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
             const size_t o = (size_t)row * g.ldp + ln.c[v];
             double2 p[LAZY];
 #pragma unroll
-            for (int j = 0; j < LAZY; ++j) p[j] = j < cnt ? ld2(ring.p[j] + o) : make_double2(0.0, 0.0);
-            double2 x = ld2(X + o);
+            for (int j = 0; j < LAZY; ++j) p[j] = j < cnt ? ldn2(ring.p[j] + o) : make_double2(0.0, 0.0);
+            double2 x = ldn2(X + o);
 #pragma unroll
             for (int j = 0; j < LAZY; ++j) {
                 if (j < cnt) {
@@ -385,7 +410,7 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
                     x.y = fma(al[j][v].y, p[j].y, x.y);
                 }
             }
-            st2(X + o, x);
+            stn2(X + o, x);
         }
     }
 }
@@ -417,8 +442,8 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
             for (int v = 0; v < NV; ++v) {
                 const size_t o = (size_t)row * g.ldp + ln.c[v];
                 const bool on = rv && ln.ok[v];
-                r[u][v] = on ? ld2(R + o) : make_double2(0.0, 0.0);
-                p[u][v] = (on && beta) ? ld2(P + o) : make_double2(0.0, 0.0);
+                r[u][v] = on ? ldn2(R + o) : make_double2(0.0, 0.0);
+                p[u][v] = (on && beta) ? ldn2(P + o) : make_double2(0.0, 0.0);
             }
         }
 #pragma unroll
@@ -434,7 +459,7 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
                 } else {
                     pn = make_double2(r[u][v].x * di[u], r[u][v].y * di[u]);
                 }
-                st2(Pout + (size_t)row * g.ldp + ln.c[v], pn);
+                stn2(Pout + (size_t)row * g.ldp + ln.c[v], pn);
             }
         }
     }
