@@ -31,8 +31,9 @@ namespace {
 
 using namespace zi;
 
-constexpr int BLOCK = 256;           // 4 waves
-constexpr int TARGET_BLOCKS = 2048;  // row tiles x column chunks per launch
+constexpr int BLOCK = 256;                         // threads per block
+constexpr int WAVES = BLOCK / 64;                  // waves per block
+constexpr int TARGET_BLOCKS = 2048 * 256 / BLOCK;  // row tiles x column chunks per launch
 
 struct Geom {
     int n, ldp, ncc;      // rows, padded columns, column chunks
@@ -92,7 +93,7 @@ template <int LPR, int NV>
 struct Lane {
     static constexpr int RPW = 64 / LPR;
     static constexpr int CW = 2 * LPR * NV;
-    static constexpr int RSTEP = 4 * RPW;
+    static constexpr int RSTEP = WAVES * RPW;
     int w, r, lr, slot;
     int c[NV];
     bool ok[NV];
@@ -202,18 +203,22 @@ __device__ __forceinline__ double bcast(double v, int u) {
 // acc = sum_k a_k X[j_k, c..c+1] over row `row`, in column order.  The row's
 // (column, value) pairs are fetched BATCH at a time with one coalesced load
 // (lane u of the group holds entry u) and broadcast, so all gathers of X for
-// the batch are in flight together.
+// the batch are in flight together.  xs receives X[row, c..c+1] (the gather
+// of the diagonal entry; self tells whether the row has one), which spares
+// the dot product a second load of the row.
 template <int LPR, int NV, class T>
 __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
                                             const int32_t *__restrict__ ci,
                                             const T *__restrict__ va,
                                             const T *__restrict__ X, int ldp, int row,
                                             int lr, const int c[NV], const bool ok[NV],
-                                            typename Pair<T>::type acc[NV]) {
+                                            typename Pair<T>::type acc[NV],
+                                            typename Pair<T>::type xs[NV], bool &self) {
     using PT = Pair<T>;
     constexpr int BATCH = LPR < 8 ? LPR : 8;
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = PT::zero();
+    self = false;
     const int s = rp[row], e = rp[row + 1];
     for (int kb = s; kb < e; kb += BATCH) {
         const int cnt = e - kb;
@@ -224,12 +229,13 @@ __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
             av = __builtin_nontemporal_load(va + kb + lr);
         }
         typename PT::type x[BATCH][NV];
+        int jj[BATCH];
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
-            const int j = bcast<LPR>(jv, u);
+            jj[u] = bcast<LPR>(jv, u);
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                x[u][v] = (u < cnt && ok[v]) ? PT::load(X + (size_t)j * ldp + c[v]) : PT::zero();
+                x[u][v] = (u < cnt && ok[v]) ? PT::load(X + (size_t)jj[u] * ldp + c[v]) : PT::zero();
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
@@ -239,6 +245,11 @@ __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
                 for (int v = 0; v < NV; ++v) {
                     acc[v].x = fma(a, x[u][v].x, acc[v].x);
                     acc[v].y = fma(a, x[u][v].y, acc[v].y);
+                }
+                if (jj[u] == row) {
+                    self = true;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) xs[v] = x[u][v];
                 }
             }
         }
@@ -293,14 +304,16 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
     for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
         const int row = base + ln.slot;
         if (row >= sc.re) continue;
-        typename PT::type acc[NV];
-        row_product<LPR, NV, T>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc);
+        typename PT::type acc[NV], xs[NV];
+        bool self;
+        row_product<LPR, NV, T>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc, xs, self);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (!ln.ok[v]) continue;
             PT::store_nt(Y + (size_t)row * g.ldp + ln.c[v], acc[v]);
             if (WITH_DOT) {
-                const double2 p = PT::widen(PT::load(X + (size_t)row * g.ldp + ln.c[v]));
+                const double2 p =
+                    PT::widen(self ? xs[v] : PT::load(X + (size_t)row * g.ldp + ln.c[v]));
                 const double2 q = PT::widen(acc[v]);
                 dotacc[0][v].x = fma(p.x, q.x, dotacc[0][v].x);
                 dotacc[0][v].y = fma(p.y, q.y, dotacc[0][v].y);
@@ -694,7 +707,7 @@ int auto_tile(int ldp) {
 Geom make_geom(int n, int ldp, int tile) {
     const TileCfg &t = kTiles[tile];
     const int cw = 2 * t.lpr * t.nv;
-    const int rstep = 4 * (64 / t.lpr);
+    const int rstep = WAVES * (64 / t.lpr);
     Geom g{};
     g.n = n;
     g.ldp = ldp;
