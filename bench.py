@@ -12,7 +12,6 @@ with 128 electrodes and 10 000 dipoles x 3 orientations.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -25,7 +24,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "LF build s and electrode-solves/s at rel.resid 1e-8; SpMM HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1811_07717_amd/csrc/k_pcg.hip"]
 
 
 def parse():
@@ -47,14 +45,6 @@ def parse():
     return p.parse_args()
 
 
-def source_hash():
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_for(kernel, workload):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
@@ -64,6 +54,7 @@ def traffic_for(kernel, workload):
     with open(path) as f:
         d = json.load(f)
     e = d.get(workload, {}).get(kernel)
+    from paper_1811_07717_amd.counters import source_hash
     if not e or e.get("source_hash") != source_hash():
         return None
     return e.get("bytes_per_launch")

@@ -1,0 +1,127 @@
+"""HBM bytes per kernel launch from two rocprofv3 counter passes.
+
+    rocprofv3 --pmc FETCH_SIZE ... -f csv -d F -o run -- python3 bench.py ... --calib-copy-mb M
+    rocprofv3 --pmc WRITE_SIZE ... -f csv -d W -o run -- python3 bench.py ... --calib-copy-mb M
+    python -m paper_1811_07717_amd.counters --fetch F/run_counter_collection.csv \
+        --write W/run_counter_collection.csv --copy-mib 2048 --workload sphere2mm_L128 \
+        --bench bench.json --update profiles/traffic.json --md profiles/x.md
+
+Both counters report KiB per dispatch.  Each is calibrated on the library's
+plain copy (zi_copy_probe, kernel k_copy2) recorded in the same pass, whose
+true traffic is known (copy_mib read and copy_mib written per launch):
+factor = true KiB / counted KiB.  The solver kernels' calibrated bytes per
+launch go to traffic.json together with a hash of the kernel sources, so
+that bench.py reports them only while the kernels are unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_1811_07717_amd/csrc/k_pcg.hip",
+                  "paper_1811_07717_amd/csrc/k_assemble.hip"]
+
+# rocprofv3 kernel name -> solver kernel key used by bench.py
+KERNELS = [(re.compile(r"k_spmm<.*, true>"), "spmm_pq"),
+           (re.compile(r"k_update<"), "update"),
+           (re.compile(r"k_pupdate<"), "pupdate"),
+           (re.compile(r"k_xflush<"), "xflush"),
+           (re.compile(r"k_copy2"), "copy")]
+
+
+def source_hash():
+    """Hash of the sources that define the solver kernels and the row order."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def per_kernel(path):
+    """Mean counter value (KiB) and launch count per solver kernel key."""
+    vals = collections.defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            for pat, key in KERNELS:
+                if pat.search(r["Kernel_Name"]):
+                    vals[key].append(float(r["Counter_Value"]))
+                    break
+    return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
+
+
+def summarize(fetch_csv, write_csv, copy_mib):
+    fe, wr = per_kernel(fetch_csv), per_kernel(write_csv)
+    if "copy" not in fe or "copy" not in wr:
+        raise SystemExit("no k_copy2 launch in the counter files (run bench.py --calib-copy-mb)")
+    true_kib = copy_mib * 1024.0
+    ff, wf = true_kib / fe["copy"][0], true_kib / wr["copy"][0]
+    out = {}
+    for k in fe:
+        if k == "copy" or k not in wr:
+            continue
+        fk, wk = fe[k][0], wr[k][0]
+        out[k] = dict(fetch_kib=round(fk, 1), write_kib=round(wk, 1),
+                      bytes_per_launch=int(round((fk * ff + wk * wf) * 1024)),
+                      launches=fe[k][1])
+    return out, ff, wf
+
+
+def main():
+    p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    p.add_argument("--fetch", required=True)
+    p.add_argument("--write", required=True)
+    p.add_argument("--copy-mib", type=float, required=True,
+                   help="MiB read (and written) by each calibration copy launch")
+    p.add_argument("--workload", required=True)
+    p.add_argument("--bench", help="bench.py JSON line (for the algorithmic bytes)")
+    p.add_argument("--update", help="traffic.json to update")
+    p.add_argument("--md", help="write a markdown table here")
+    p.add_argument("--command", default="", help="command line to record in the table")
+    a = p.parse_args()
+    res, ff, wf = summarize(a.fetch, a.write, a.copy_mib)
+    alg = {}
+    if a.bench:
+        with open(a.bench) as f:
+            line = [ln for ln in f.read().splitlines() if ln.startswith("{")][-1]
+        alg = {k: v["bytes_per_launch"] for k, v in json.loads(line)["solver_kernels"].items()}
+    h = source_hash()
+    if a.update:
+        d = {}
+        if os.path.exists(a.update):
+            with open(a.update) as f:
+                d = json.load(f)
+        w = d.setdefault(a.workload, {})
+        for k, v in res.items():
+            w[k] = dict(v, source_hash=h, fetch_factor=round(ff, 4), write_factor=round(wf, 4))
+        with open(a.update, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+            f.write("\n")
+    rows = ["| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes/launch "
+            "(calibrated) | algorithmic bytes | ratio |", "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(res.items()):
+        ab = alg.get(k)
+        ratio = f"{v['bytes_per_launch'] / ab:.3f}" if ab else "-"
+        rows.append(f"| {k} | {v['launches']} | {v['fetch_kib']:.1f} | {v['write_kib']:.1f} | "
+                    f"{v['bytes_per_launch']:,} | {ab:,} | {ratio} |" if ab else
+                    f"| {k} | {v['launches']} | {v['fetch_kib']:.1f} | {v['write_kib']:.1f} | "
+                    f"{v['bytes_per_launch']:,} | - | - |")
+    text = "\n".join(rows) + (f"\n\nCalibration on k_copy2 ({a.copy_mib:g} MiB read + written per "
+                              f"launch): FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f}. "
+                              f"Kernel source hash {h}.\n")
+    if a.md:
+        with open(a.md, "w") as f:
+            if a.command:
+                f.write(a.command.strip() + "\n\n")
+            f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()
