@@ -140,11 +140,14 @@ class WarmStart:
             order = rng.permutation(len(data))
             tot = 0.0
             rate = lr * (0.5 ** ep)
-            for k in order:
+            for i, k in enumerate(order):
                 X, t = data[k]
                 loss, _ = self.net.loss_grad(X, t)
                 self.net.adam_step(rate)
                 tot += loss
+                if (i + 1) % max(1, len(data) // 4) == 0 and i + 1 < len(data):
+                    self.log(f"[warmstart] epoch {ep + 1}: {i + 1}/{len(data)} steps, "
+                             f"mean loss {tot / (i + 1):.4f} ({time.time() - t0:.0f} s)")
             hist.append(tot / len(data))
             self.log(f"[warmstart] epoch {ep + 1}/{epochs}: mean loss {hist[-1]:.4f} "
                      f"({time.time() - t0:.0f} s)")
@@ -175,4 +178,6 @@ class WarmStart:
                              time.perf_counter() - ta)
             s.close()
             rows.append(res)
+            if (f + 1) % max(1, n_fields // 10) == 0:
+                self.log(f"[warmstart] eval: field {f + 1}/{n_fields}")
         return rows
