@@ -97,7 +97,8 @@ typedef struct {
     int32_t precond;     /* ZI_PREC_JACOBI or ZI_PREC_LDP */
     int32_t precision;   /* ZI_FP64 or ZI_FP32_SPMM_IR */
     int32_t check_every; /* iterations between host convergence checks; 0 -> 8 */
-    int32_t timing;      /* 1: time the solver kernels with HIP events */
+    int32_t timing;      /* 1: time the solver kernels with HIP events
+                            (the launches of every 8th iteration) */
     int32_t tile;        /* SpMM tile id (see zi_tile_count); -1 -> the tile
                             zi_autotune chose, else a width-based default */
     int32_t graph;       /* 1: replay the iteration loop as a hipGraph of
@@ -121,7 +122,7 @@ typedef struct {
     int32_t tile;          /* SpMM tile used */
     int32_t n_kernels;     /* entries used in the arrays below */
     double kernel_ms[8];   /* total event-timed ms per solver kernel */
-    int32_t kernel_launches[8];
+    int32_t kernel_launches[8]; /* launches timed (a sample of every 8th) */
     int64_t kernel_bytes[8]; /* algorithmic bytes of one launch */
     const char *kernel_name[8];
 } zi_solve_stats;

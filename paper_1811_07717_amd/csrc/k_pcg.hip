@@ -385,7 +385,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
 }
 
 // Ring of the last LAZY search directions and their step lengths.
-constexpr int LAZY = 4;
+constexpr int LAZY = 8;
 template <class TP>
 struct Ring {
     const TP *p[LAZY];
@@ -798,7 +798,7 @@ __global__ void k_dinv(const double *d, const int32_t *perm, int32_t n, double *
 struct zi_solver_ws {
     int ldp = 0, nrt_cap = 0;
     double *X = nullptr, *R = nullptr, *Q = nullptr, *dinv = nullptr;
-    double *P[LAZY] = {nullptr, nullptr, nullptr, nullptr};   // search-direction ring
+    double *P[LAZY] = {};                                     // search-direction ring
     double *aring = nullptr;                                  // LAZY x ldp step lengths
     double *aflush = nullptr;                                 // LAZY x ldp scratch
     double *part[3] = {nullptr, nullptr, nullptr};
@@ -923,14 +923,21 @@ zi_status read_active(SolveCtx &c, hipStream_t s) {
     return ZI_OK;
 }
 
+// Kernel timing samples one iteration in TIMING_STRIDE (events between
+// dependent kernels add a few microseconds each); the statistics report the
+// sampled launches and their total time.
+constexpr int TIMING_STRIDE = 8;
+
 struct Timed {
     SolveCtx &c;
     int which;
     hipStream_t s;
     hipEvent_t e1 = nullptr;
     zi_status st = ZI_OK;
-    Timed(SolveCtx &c_, int w, hipStream_t s_) : c(c_), which(w), s(s_) {
-        if (!c.timing) return;
+    bool on;
+    Timed(SolveCtx &c_, int w, hipStream_t s_, bool sample)
+        : c(c_), which(w), s(s_), on(c_.timing && sample) {
+        if (!on) return;
         hipEvent_t e0;
         if ((st = c.timer.get(&e0)) != ZI_OK || (st = c.timer.get(&e1)) != ZI_OK) return;
         c.ev[which].push_back(e0);
@@ -938,7 +945,7 @@ struct Timed {
         (void)hipEventRecord(e0, s);
     }
     ~Timed() {
-        if (c.timing && e1) (void)hipEventRecord(e1, s);
+        if (on && e1) (void)hipEventRecord(e1, s);
     }
 };
 
@@ -956,7 +963,7 @@ zi_status enqueue_flush(SolveCtx &c, int it_end, hipStream_t s) {
     double *al = c.ws->aring;
     const int first = c.flushed % LAZY;
     {
-        Timed t(c, 3, s);
+        Timed t(c, 3, s, cnt == LAZY && (it_end / LAZY) % (TIMING_STRIDE / LAZY) == 0);
         ZI_TRY(t.st);
         if (first == 0) {
             ZI_TILE_SWITCH(c.tile, launch_xflush, c.g, s, cnt, (const double *)al, ring, c.ws->X);
@@ -989,14 +996,14 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const TP *va, hipStream_t s, boo
     TP *Q = reinterpret_cast<TP *>(ws->Q);
     double *al = c.alpha(k);
     {
-        Timed t(c, 0, s);
+        Timed t(c, 0, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
         ZI_TILE_SWITCH(tile, launch_spmm, g, s, c.sys->sp_ptr, c.sys->sp_col, va, (const TP *)Pk,
                        Q, ws->part[0]);
     }
     hipLaunchKernelGGL(k_red_alpha, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt);
     {
-        Timed t(c, 1, s);
+        Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
         ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)al, (const double *)ws->dinv,
                        ws->R, (const TP *)Q, ws->part[1], ws->part[2]);
@@ -1006,7 +1013,7 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const TP *va, hipStream_t s, boo
     hipLaunchKernelGGL(k_red_beta, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[1], ws->part[2],
                        g.nrt);
     {
-        Timed t(c, 2, s);
+        Timed t(c, 2, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
         ZI_TILE_SWITCH(tile, launch_pupdate, g, s, (const double *)c.sc.beta,
                        (const double *)ws->dinv, (const double *)ws->R, (const TP *)Pk, Pn);
