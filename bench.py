@@ -36,6 +36,9 @@ def parse():
     p.add_argument("--precond", default="jacobi")
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32_spmm_ir"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-mixed", action="store_true",
+                   help="skip the second timing of the same builds with the mixed-precision "
+                        "solve (fp32 search directions and products, fp64 recurrences)")
     p.add_argument("--sweep-tiles", action="store_true",
                    help="also time zi_spmm with every tile on an n x L block")
     p.add_argument("--calib-copy-mb", type=int, default=0,
@@ -149,6 +152,44 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
 
+    mixed = None
+    if a.precision == "fp64" and cols is None and not a.no_mixed:
+        # the same builds with ZI_FP32_SPMM_IR, timed separately; the lead field
+        # is compared with the FP64 one just computed
+        LF64 = LF.clone()
+        s1 = zi.System(nodes, tets, sigma, tris, tre, H.Z)
+        bm, _ = s1.autotune("fp32_spmm_ir")
+        s1.close()
+
+        def mstep():
+            s = zi.System(nodes, tets, sigma, tris, tre, H.Z)
+            _, st = s.transfer_solve(tol=1e-8, precond=a.precond, precision="fp32_spmm_ir",
+                                     tile=bm, out=T)
+            s.leadfield(T, G, out=LF)
+            s.close()
+            return st
+
+        for _ in range(a.warmup):
+            mstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mst = [mstep() for _ in range(a.steps)]
+        torch.cuda.synchronize()
+        dtm = (time.perf_counter() - t0) / a.steps
+        n64 = LF64.norm(dim=0)
+        nm = LF.norm(dim=0)
+        rdm = (LF / nm - LF64 / n64).norm(dim=0)
+        mixed = {"value": L / dtm, "ms_per_step": dtm * 1e3, "tile": zi.tile_names()[bm],
+                 "pcg_iters": {"median": int(np.median(mst[-1]["iters"])),
+                               "max": int(mst[-1]["iters"].max()),
+                               "refinements": int(mst[-1]["refinements"])},
+                 "true_relres_max": float(max(np.max(x["relres_true"]) for x in mst)),
+                 "lf_rdm_vs_fp64_max": float(rdm.max()),
+                 "lf_mag_vs_fp64_max": float((nm / n64 - 1).abs().max()),
+                 "dtype": "f32 search directions and products; f64 matrix values, sums, "
+                          "dots and recurrences"}
+        del LF64
+
     if a.calib_copy_mb:
         x = torch.ones((a.calib_copy_mb << 20) // 8, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
@@ -215,6 +256,8 @@ def main():
         out["autotune"] = tuned
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(H, K)
+    if mixed is not None:
+        out["mixed_precision"] = mixed
     print(json.dumps(out))
 
 

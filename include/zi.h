@@ -86,8 +86,12 @@ enum { ZI_PREC_JACOBI = 0, /* D_ii = a_ii */
        ZI_PREC_LDP = 1     /* lumped diagonal D_ii = sum_j |a_ij| (Sec. 2.3.1) */ };
 
 enum { ZI_FP64 = 0,         /* all arithmetic in float64 */
-       ZI_FP32_SPMM_IR = 1  /* float32 matrix products inside float64 PCG
-                               recurrences, with float64 iterative refinement */ };
+       ZI_FP32_SPMM_IR = 1  /* float32 search directions and products (float64
+                               matrix values, float64 sums) inside float64 PCG
+                               recurrences; the recurrence residual is replaced
+                               by the float64 true residual every 64 iterations,
+                               and columns whose true residual misses tol at the
+                               end restart (float64 iterative refinement) */ };
 
 /* Options of zi_transfer_solve.  Zero-initialised fields take defaults. */
 typedef struct {

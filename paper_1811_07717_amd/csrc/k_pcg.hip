@@ -148,29 +148,45 @@ __device__ __forceinline__ void stn2(float *p, double2 v) {
     __builtin_nontemporal_store((float)v.y, p + 1);
 }
 
-template <class T>
-struct Pair;
+// Column pairs of the SpMM.  Sums accumulate in the precision of the matrix
+// values (Acc<TV>); the block vectors may be narrower (double values with
+// float vectors widen on load and round on store).
+template <class TV>
+struct Acc;
 template <>
-struct Pair<double> {
+struct Acc<double> {
     using type = double2;
     __device__ static double2 zero() { return make_double2(0.0, 0.0); }
-    __device__ static double2 load(const double *p) { return *reinterpret_cast<const double2 *>(p); }
-    __device__ static void store(double *p, double2 v) { *reinterpret_cast<double2 *>(p) = v; }
-    __device__ static void store_nt(double *p, double2 v) { stn2(p, v); }
-    __device__ static double2 widen(double2 v) { return v; }
 };
 template <>
-struct Pair<float> {
+struct Acc<float> {
     using type = float2;
     __device__ static float2 zero() { return make_float2(0.f, 0.f); }
-    __device__ static float2 load(const float *p) { return *reinterpret_cast<const float2 *>(p); }
-    __device__ static void store(float *p, float2 v) { *reinterpret_cast<float2 *>(p) = v; }
-    __device__ static void store_nt(float *p, float2 v) {
-        __builtin_nontemporal_store(v.x, p);
-        __builtin_nontemporal_store(v.y, p + 1);
-    }
-    __device__ static double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
 };
+__device__ __forceinline__ void ldpair(const double *p, double2 &v) {
+    v = *reinterpret_cast<const double2 *>(p);
+}
+__device__ __forceinline__ void ldpair(const float *p, double2 &v) {
+    const float2 f = *reinterpret_cast<const float2 *>(p);
+    v = make_double2((double)f.x, (double)f.y);
+}
+__device__ __forceinline__ void ldpair(const float *p, float2 &v) {
+    v = *reinterpret_cast<const float2 *>(p);
+}
+__device__ __forceinline__ void stpair_nt(double *p, double2 v) { stn2(p, v); }
+__device__ __forceinline__ void stpair_nt(float *p, double2 v) { stn2(p, v); }
+__device__ __forceinline__ void stpair_nt(float *p, float2 v) {
+    __builtin_nontemporal_store(v.x, p);
+    __builtin_nontemporal_store(v.y, p + 1);
+}
+__device__ __forceinline__ double2 wide(double2 v) { return v; }
+__device__ __forceinline__ double2 wide(float2 v) { return make_double2((double)v.x, (double)v.y); }
+// v as a block vector of type TX stores it, in FP64
+__device__ __forceinline__ double2 as_stored(double2 v, const double *) { return v; }
+__device__ __forceinline__ double2 as_stored(double2 v, const float *) {
+    return make_double2((double)(float)v.x, (double)(float)v.y);
+}
+__device__ __forceinline__ double2 as_stored(float2 v, const float *) { return wide(v); }
 
 // Broadcast lane u of the LPR-lane row group (readlane when one row fills
 // the wave, a cross-lane permute otherwise).
@@ -206,45 +222,49 @@ __device__ __forceinline__ double bcast(double v, int u) {
 // the batch are in flight together.  xs receives X[row, c..c+1] (the gather
 // of the diagonal entry; self tells whether the row has one), which spares
 // the dot product a second load of the row.
-template <int LPR, int NV, class T>
+template <int LPR, int NV, class TV, class TX>
 __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
                                             const int32_t *__restrict__ ci,
-                                            const T *__restrict__ va,
-                                            const T *__restrict__ X, int ldp, int row,
+                                            const TV *__restrict__ va,
+                                            const TX *__restrict__ X, int ldp, int row,
                                             int lr, const int c[NV], const bool ok[NV],
-                                            typename Pair<T>::type acc[NV],
-                                            typename Pair<T>::type xs[NV], bool &self) {
-    using PT = Pair<T>;
+                                            typename Acc<TV>::type acc[NV],
+                                            typename Acc<TX>::type xs[NV], bool &self) {
+    using XT = typename Acc<TX>::type;   // gathered pairs stay in storage precision
     constexpr int BATCH = LPR < 8 ? LPR : 8;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = PT::zero();
+    for (int v = 0; v < NV; ++v) acc[v] = Acc<TV>::zero();
     self = false;
     const int s = rp[row], e = rp[row + 1];
     for (int kb = s; kb < e; kb += BATCH) {
         const int cnt = e - kb;
         int jv = row;
-        T av = T(0);
+        TV av = TV(0);
         if (lr < BATCH && lr < cnt) {
             jv = __builtin_nontemporal_load(ci + kb + lr);
             av = __builtin_nontemporal_load(va + kb + lr);
         }
-        typename PT::type x[BATCH][NV];
+        XT x[BATCH][NV];
         int jj[BATCH];
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
             jj[u] = bcast<LPR>(jv, u);
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                x[u][v] = (u < cnt && ok[v]) ? PT::load(X + (size_t)jj[u] * ldp + c[v]) : PT::zero();
+            for (int v = 0; v < NV; ++v) {
+                if (u < cnt && ok[v])
+                    ldpair(X + (size_t)jj[u] * ldp + c[v], x[u][v]);
+                else
+                    x[u][v] = Acc<TX>::zero();
+            }
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
-            const T a = bcast<LPR>(av, u);
+            const TV a = bcast<LPR>(av, u);
             if (u < cnt) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    acc[v].x = fma(a, x[u][v].x, acc[v].x);
-                    acc[v].y = fma(a, x[u][v].y, acc[v].y);
+                    acc[v].x = fma(a, (TV)x[u][v].x, acc[v].x);
+                    acc[v].y = fma(a, (TV)x[u][v].y, acc[v].y);
                 }
                 if (jj[u] == row) {
                     self = true;
@@ -287,14 +307,16 @@ __device__ __forceinline__ void block_partials(const Geom &g, const Lane<LPR, NV
 
 // ---------------------------------------------------------------------------
 
-// Y = A X; with WITH_DOT also the partials of sum_i X[i,c] Y[i,c] (in FP64).
-template <int LPR, int NV, class T, bool WITH_DOT>
+// Y = A X; with WITH_DOT also the partials of sum_i X[i,c] Y[i,c] (in FP64,
+// with Y as stored).
+template <int LPR, int NV, class TV, class TX, bool WITH_DOT>
 __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ ci,
-                                                const T *__restrict__ va,
-                                                const T *__restrict__ X, T *__restrict__ Y,
+                                                const TV *__restrict__ va,
+                                                const TX *__restrict__ X, TX *__restrict__ Y,
                                                 double *part) {
-    using PT = Pair<T>;
+    using AT = typename Acc<TV>::type;
+    using XT = typename Acc<TX>::type;
     Sched sc;
     if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
     Lane<LPR, NV> ln(g, sc.cc);
@@ -304,17 +326,20 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
     for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
         const int row = base + ln.slot;
         if (row >= sc.re) continue;
-        typename PT::type acc[NV], xs[NV];
+        AT acc[NV];
+        XT xs[NV];
         bool self;
-        row_product<LPR, NV, T>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc, xs, self);
+        row_product<LPR, NV, TV, TX>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc, xs, self);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (!ln.ok[v]) continue;
-            PT::store_nt(Y + (size_t)row * g.ldp + ln.c[v], acc[v]);
+            TX *y = Y + (size_t)row * g.ldp + ln.c[v];
+            stpair_nt(y, acc[v]);
             if (WITH_DOT) {
-                const double2 p =
-                    PT::widen(self ? xs[v] : PT::load(X + (size_t)row * g.ldp + ln.c[v]));
-                const double2 q = PT::widen(acc[v]);
+                XT xr = xs[v];
+                if (!self) ldpair(X + (size_t)row * g.ldp + ln.c[v], xr);
+                const double2 p = wide(xr);
+                const double2 q = as_stored(acc[v], (const TX *)y);
                 dotacc[0][v].x = fma(p.x, q.x, dotacc[0][v].x);
                 dotacc[0][v].y = fma(p.y, q.y, dotacc[0][v].y);
             }
@@ -543,8 +568,9 @@ struct Scal {
 
 constexpr int RED = 256;
 
-// Default interval of the reliable updates of the mixed-precision solve.
-constexpr int MIXED_CHECK = 16;
+// The mixed-precision solve replaces the recurrence residual by the FP64
+// true residual after every MIXED_REPLACE-th iteration (a multiple of LAZY).
+constexpr int MIXED_REPLACE = 64;
 
 __device__ __forceinline__ double col_sum(const double *part, int nrt, int c) {
     __shared__ double s[RED];
@@ -739,15 +765,15 @@ Geom make_geom(int n, int ldp, int tile) {
     return g;
 }
 
-template <int LPR, int NV, class T>
-void launch_spmm(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t *ci, const T *va,
-                 const T *X, T *Y, double *part) {
+template <int LPR, int NV, class TV, class TX>
+void launch_spmm(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t *ci,
+                 const TV *va, const TX *X, TX *Y, double *part) {
     if (part)
-        hipLaunchKernelGGL((k_spmm<LPR, NV, T, true>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, rp,
-                           ci, va, X, Y, part);
+        hipLaunchKernelGGL((k_spmm<LPR, NV, TV, TX, true>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g,
+                           rp, ci, va, X, Y, part);
     else
-        hipLaunchKernelGGL((k_spmm<LPR, NV, T, false>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, rp,
-                           ci, va, X, Y, part);
+        hipLaunchKernelGGL((k_spmm<LPR, NV, TV, TX, false>), dim3(g.nb_pad), dim3(BLOCK), 0, s,
+                           g, rp, ci, va, X, Y, part);
 }
 
 template <int LPR, int NV, class TP>
@@ -983,12 +1009,13 @@ zi_status enqueue_flush(SolveCtx &c, int it_end, hipStream_t s) {
 
 // Enqueue iteration k (no host synchronisation): SpMM with p.q, alpha, the
 // residual update, every LAZY-th iteration the X flush, beta and the next
-// direction into the ring.  TP is the element type of P and Q (the matrix
-// values have the same type).  replace_r: after the flush, overwrite r by the
+// direction into the ring.  TP is the element type of P and Q; the matrix
+// values are FP64 in both modes.  replace_r: after the flush, overwrite r by the
 // FP64 true residual b - A x before beta (a reliable update: the search
 // direction is kept, only the drift of the recurrence is removed).
 template <class TP>
-zi_status enqueue_iteration(SolveCtx &c, int k, const TP *va, hipStream_t s, bool replace_r) {
+zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
+                            bool replace_r) {
     zi_solver_ws *ws = c.ws;
     const Geom &g = c.g;
     const int tile = c.tile;
@@ -1022,13 +1049,14 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const TP *va, hipStream_t s, boo
     return ZI_OK;
 }
 
-// Iterations it .. it+count-1.  In the mixed-precision mode the last
-// iteration of every chunk is a reliable update.
+// Iterations it .. it+count-1.  In the mixed-precision mode iteration k is a
+// reliable update when (k + 1) % MIXED_REPLACE == 0.
 zi_status enqueue_iterations(SolveCtx &c, int count, hipStream_t s) {
     const int it0 = c.it;
     for (int j = 0; j < count; ++j) {
         if (c.mixed) {
-            ZI_TRY(enqueue_iteration<float>(c, it0 + j, c.sys->sp_val32, s, j == count - 1));
+            ZI_TRY(enqueue_iteration<float>(c, it0 + j, c.sys->sp_val, s,
+                                            (it0 + j + 1) % MIXED_REPLACE == 0));
         } else {
             ZI_TRY(enqueue_iteration<double>(c, it0 + j, c.sys->sp_val, s, false));
         }
@@ -1118,12 +1146,6 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     c.mixed = o->precision == ZI_FP32_SPMM_IR;
     ZI_TRY(ensure_ws(sys, ldp, max_nrt(n, ldp)));
     zi_solver_ws *ws = sys->ws;
-    if (c.mixed && !sys->sp_val32) {
-        ZI_TRY(sys->pool.alloc(&sys->sp_val32, (size_t)sys->sp_nnz));
-        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((sys->sp_nnz + 255) / 256)), dim3(256), 0, s,
-                           sys->sp_val, sys->sp_nnz, sys->sp_val32);
-        ZI_HIP(hipGetLastError());
-    }
     c.sys = sys;
     c.ws = ws;
     c.g = make_geom(n, ldp, tile);
@@ -1131,8 +1153,13 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     c.ldp = ldp;
     c.L = L;
     c.maxit = o->maxit > 0 ? o->maxit : 50000;
-    c.check = o->check_every > 0 ? o->check_every : (c.mixed ? MIXED_CHECK : 8);
+    c.check = o->check_every > 0 ? o->check_every : 8;
     c.check = ((c.check + LAZY - 1) / LAZY) * LAZY;   // chunks end on an X flush
+    if (c.mixed) {   // a divisor of MIXED_REPLACE: captured chunks repeat per phase
+        int q = LAZY;
+        while (q < c.check && q < MIXED_REPLACE) q *= 2;
+        c.check = q;
+    }
     c.tol = o->tol > 0 ? o->tol : 1e-8;
     c.tol2 = c.tol * c.tol;
     c.eta2 = 0.0;
@@ -1241,7 +1268,7 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
         if (c.timing) {
             const int64_t pe = c.mixed ? 4 : 8;   // bytes of a P or Q entry
             const int64_t ne = (int64_t)n * ldp;
-            const int64_t abytes = (int64_t)c.sys->sp_nnz * (4 + pe) + (int64_t)(n + 1) * 4;
+            const int64_t abytes = (int64_t)c.sys->sp_nnz * 12 + (int64_t)(n + 1) * 4;
             static const char *names[4] = {"spmm_pq", "update", "pupdate", "xflush"};
             const int64_t bytes[4] = {
                 abytes + 2 * pe * ne,                      // read P, write Q
@@ -1279,6 +1306,26 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
 // branch per solve (its own stream), forked from and joined back to the
 // internal capture stream `origin` (never the caller's stream, which may be
 // the null stream).  The graph is launched on the caller's stream.
+// Captured chunks of check iterations.  In the mixed mode the reliable updates
+// fall on fixed iterations, so a chunk's graph depends on its phase in the
+// MIXED_REPLACE cycle: one graph per phase.
+struct GraphSet {
+    std::vector<hipGraphExec_t> ex;
+    ~GraphSet() { clear(); }
+    void clear() {
+        for (auto e : ex)
+            if (e) (void)hipGraphExecDestroy(e);
+        ex.clear();
+    }
+    void reset(const SolveCtx &c) {
+        clear();
+        ex.assign(c.mixed ? MIXED_REPLACE / c.check : 1, nullptr);
+    }
+    static int phase(const SolveCtx &c) {
+        return c.mixed ? (c.it % MIXED_REPLACE) / c.check : 0;
+    }
+};
+
 zi_status capture_graph(std::vector<SolveCtx *> &cs, std::vector<hipStream_t> &streams,
                         int count, hipStream_t origin, hipGraphExec_t *exec) {
     hipEvent_t fork, join_ev;
@@ -1332,8 +1379,8 @@ zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_so
         ZI_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
         ZI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         std::vector<hipStream_t> streams{side};
-        hipGraphExec_t exec = nullptr;
-        int exec_chunk = 0;
+        GraphSet gs;
+        gs.reset(c);
         zi_status r = ZI_OK;
         while (!c.done && r == ZI_OK) {
             const int chunk = c.check;
@@ -1344,12 +1391,10 @@ zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_so
                 r = solve_check(c, s);
                 continue;
             }
-            if (!exec || chunk != exec_chunk) {
-                if (exec) (void)hipGraphExecDestroy(exec);
-                exec = nullptr;
+            hipGraphExec_t &exec = gs.ex[GraphSet::phase(c)];
+            if (!exec) {
                 r = capture_graph(cs, streams, chunk, cap, &exec);
                 if (r != ZI_OK) break;
-                exec_chunk = chunk;
             }
             if (hipGraphLaunch(exec, s) != hipSuccess) {
                 set_error("hipGraphLaunch failed");
@@ -1360,7 +1405,7 @@ zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_so
             c.flushed = c.it;   // every chunk ends on an X flush (chunk % LAZY == 0)
             r = solve_check(c, s);
         }
-        if (exec) (void)hipGraphExecDestroy(exec);
+        gs.clear();
         (void)hipStreamDestroy(side);
         (void)hipStreamDestroy(cap);
         ZI_TRY(r);
@@ -1392,7 +1437,7 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
         }
     } guard{streams};
     const int chunk = cs[0].check;   // same options for every system
-    hipGraphExec_t exec = nullptr;
+    GraphSet gs;
     std::vector<int> members, last;
     zi_status r = ZI_OK;
     for (;;) {
@@ -1410,9 +1455,12 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
             }
         }
         if (r != ZI_OK || members.empty()) break;
-        if (members != last) {
-            if (exec) (void)hipGraphExecDestroy(exec);
-            exec = nullptr;
+        if (members != last) {   // members share the iteration count (and phase)
+            gs.reset(cs[members[0]]);
+            last = members;
+        }
+        hipGraphExec_t &exec = gs.ex[GraphSet::phase(cs[members[0]])];
+        if (!exec) {
             std::vector<SolveCtx *> sel;
             std::vector<hipStream_t> ss;
             for (int k : members) {
@@ -1421,7 +1469,6 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
             }
             r = capture_graph(sel, ss, chunk, cap, &exec);
             if (r != ZI_OK) break;
-            last = members;
         }
         if (hipGraphLaunch(exec, s) != hipSuccess) {
             set_error("hipGraphLaunch failed");
@@ -1436,7 +1483,7 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
         }
         if (r != ZI_OK) break;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
+    gs.clear();
     ZI_TRY(r);
     zi_status worst = ZI_OK;
     for (int k = 0; k < nsys; ++k) {
@@ -1455,11 +1502,6 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     }
     ZI_TRY(ensure_ws(sys, ldp, max_nrt(n, ldp)));
     zi_solver_ws *ws = sys->ws;
-    if (precision == ZI_FP32_SPMM_IR && !sys->sp_val32) {
-        ZI_TRY(sys->pool.alloc(&sys->sp_val32, (size_t)sys->sp_nnz));
-        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((sys->sp_nnz + 255) / 256)), dim3(256), 0, s,
-                           sys->sp_val, sys->sp_nnz, sys->sp_val32);
-    }
     // a smooth, non-zero block to multiply (the solver's R buffer)
     ZI_TRY(fill_f64(ws->R, 1.0, (size_t)n * ldp, s));
     if (precision == ZI_FP32_SPMM_IR)
@@ -1481,7 +1523,7 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
             ZI_HIP(hipEventRecord(e0, s));
             if (precision == ZI_FP32_SPMM_IR) {
                 ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
-                               (const float *)sys->sp_val32, (const float *)ws->P[0],
+                               (const double *)sys->sp_val, (const float *)ws->P[0],
                                reinterpret_cast<float *>(ws->Q), ws->part[0]);
             } else {
                 ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,

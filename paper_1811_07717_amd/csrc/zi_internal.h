@@ -128,7 +128,6 @@ struct zi_system {
     int32_t *perm = nullptr, *iperm = nullptr;
     int32_t *sp_ptr = nullptr, *sp_col = nullptr;
     double *sp_val = nullptr;
-    float *sp_val32 = nullptr;   // float32 copy for the mixed-precision solve
     int64_t sp_nnz = 0;
     double *diag = nullptr;      // a_ii
     double *absrow = nullptr;    // sum_j |a_ij|
