@@ -209,14 +209,16 @@ def main():
         s1.close()
         del X
 
-    # dominant kernel: the solver kernel with the largest total time
+    # dominant kernel: the largest (average launch time x launches); the
+    # library times a sample of the launches
     ktot = {}
     for st in stats:
         for k, v in st["kernels"].items():
-            e = ktot.setdefault(k, dict(ms=0.0, launches=0, bytes=v["bytes"]))
+            e = ktot.setdefault(k, dict(ms=0.0, launches=0, calls=0, bytes=v["bytes"]))
             e["ms"] += v["ms"]
             e["launches"] += v["launches"]
-    dom = max(ktot, key=lambda k: ktot[k]["ms"])
+            e["calls"] += v["calls"]
+    dom = max(ktot, key=lambda k: ktot[k]["ms"] / max(ktot[k]["launches"], 1) * ktot[k]["calls"])
     avg_ms = ktot[dom]["ms"] / ktot[dom]["launches"]
     gbs = ktot[dom]["bytes"] / (avg_ms * 1e-3) / 1e9
     iters = stats[-1]["iters"]
@@ -244,7 +246,9 @@ def main():
                       "refinements": int(stats[-1]["refinements"])},
         "solver_kernels": {k: {"avg_ms": v["ms"] / v["launches"],
                                "gbs": v["bytes"] / (v["ms"] / v["launches"] * 1e-3) / 1e9,
-                               "bytes_per_launch": v["bytes"]} for k, v in ktot.items()},
+                               "bytes_per_launch": v["bytes"],
+                               "launches_per_step": v["calls"] // a.steps,
+                               "timed_launches": v["launches"]} for k, v in ktot.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                      "traffic": traffic_for(dom, a.workload)},

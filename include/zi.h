@@ -129,6 +129,7 @@ typedef struct {
     int32_t kernel_launches[8]; /* launches timed (a sample of every 8th) */
     int64_t kernel_bytes[8]; /* algorithmic bytes of one launch */
     const char *kernel_name[8];
+    int32_t kernel_calls[8];   /* launches in the solve (timed or not) */
 } zi_solve_stats;
 
 /* Assemble the grounded CEM system of Eq. (u_system).

@@ -234,20 +234,34 @@ __global__ __launch_bounds__(ROW_THREADS) void k_row_struct(const int32_t *inc_p
 // 5. values: row-owned gather in ascending tet order
 // ---------------------------------------------------------------------------
 
+// RV lanes per row; lane j owns the row's entries s + j, s + j + RV, ... and
+// adds, over the row's incident tets in ascending tet order, the element
+// entry that couples the row to its column.  Every entry is summed in the
+// same order as a row-serial loop would (a tet has distinct vertices, so at
+// most one of its entries lands on a given column).
+constexpr int RV = 16;
+
 __global__ void k_row_values(const int32_t *inc_ptr, const int32_t *inc, const int32_t *tets,
                              const double *Ke, const int32_t *row_ptr, const int32_t *col,
                              double *val, int32_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = gid / RV;
+    const int lane = (int)(gid % RV);
     if (i >= n) return;
     const int32_t s = row_ptr[i], e = row_ptr[i + 1];
-    for (int32_t q = s; q < e; ++q) val[q] = 0.0;
-    for (int32_t p = inc_ptr[i]; p < inc_ptr[i + 1]; ++p) {
-        const int64_t t = inc[p] >> 2;
-        const int a = inc[p] & 3;
-        for (int b = 0; b < 4; ++b) {
-            const int32_t q = find_col(col, s, e, tets[4 * t + b]);
-            if (q >= 0) val[q] += Ke[10 * t + sym10(a, b)];
+    const int32_t p0 = inc_ptr[i], p1 = inc_ptr[i + 1];
+    for (int32_t q0 = s; q0 < e; q0 += RV) {
+        const int32_t q = q0 + lane;
+        const int32_t cq = q < e ? col[q] : -1;
+        double acc = 0.0;
+        for (int32_t p = p0; p < p1; ++p) {
+            const int64_t t = inc[p] >> 2;
+            const int a = inc[p] & 3;
+            const int4 v = *reinterpret_cast<const int4 *>(tets + 4 * t);
+            const int b = v.x == cq ? 0 : v.y == cq ? 1 : v.z == cq ? 2 : v.w == cq ? 3 : -1;
+            if (b >= 0) acc += Ke[10 * t + sym10(a, b)];
         }
+        if (q < e) val[q] = acc;
     }
 }
 
@@ -800,8 +814,8 @@ zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t
     ZI_HIP(hipGetLastError());
 
     // 5. stiffness values
-    hipLaunchKernelGGL(k_row_values, dim3(grid_for(n, 128)), dim3(128), 0, s, inc_ptr, inc,
-                       sys->tets, Ke, sys->row_ptr, sys->col, sys->val, n);
+    hipLaunchKernelGGL(k_row_values, dim3(grid_for((size_t)n * RV, 256)), dim3(256), 0, s,
+                       inc_ptr, inc, sys->tets, Ke, sys->row_ptr, sys->col, sys->val, n);
     ZI_HIP(hipGetLastError());
 
     // 6. boundary faces, electrode triangles on faces

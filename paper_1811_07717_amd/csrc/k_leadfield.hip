@@ -108,6 +108,88 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_w(const double *S, int L,
     }
 }
 
+// The same for L <= CHOL_LDS_MAX, in LDS: M is factored in place by a
+// right-looking Cholesky (lower triangle, rows padded to L + 1 doubles so that
+// column-parallel reads fall in different banks), L^-1 goes to the free upper
+// triangle (transposed) and its diagonal to idiag, then M^-1 = L^-T L^-1 and W.
+constexpr int CHOL_LDS_MAX = 128;
+constexpr int CHOL_LDS_THREADS = 1024;
+
+__global__ __launch_bounds__(CHOL_LDS_THREADS) void k_chol_lds(const double *S, int L,
+                                                               double *Minv, double *W,
+                                                               int *flag) {
+    __shared__ double A[CHOL_LDS_MAX * (CHOL_LDS_MAX + 1)];
+    __shared__ double idiag[CHOL_LDS_MAX];
+    __shared__ double mean[CHOL_LDS_MAX];
+    __shared__ int bad;
+    const int tid = threadIdx.x, ld = L + 1;
+    for (int idx = tid; idx < L * L; idx += CHOL_LDS_THREADS) {
+        const int i = idx / L, j = idx % L;
+        A[i * ld + j] = -0.5 * (S[(size_t)i * L + j] + S[(size_t)j * L + i]);
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < L; ++j) {
+        if (tid == 0) {
+            const double d = A[j * ld + j];
+            if (!(d > 0.0)) bad = 1;
+            A[j * ld + j] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double piv = A[j * ld + j];
+        for (int i = j + 1 + tid; i < L; i += CHOL_LDS_THREADS) A[i * ld + j] /= piv;
+        __syncthreads();
+        const int m = L - j - 1;
+        for (int idx = tid; idx < m * m; idx += CHOL_LDS_THREADS) {
+            const int i = j + 1 + idx / m, k = j + 1 + idx % m;
+            if (k <= i) A[i * ld + k] = fma(-A[i * ld + j], A[k * ld + j], A[i * ld + k]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && bad) *flag = 1;
+    // column c of L^-1: Linv[c][c] = 1 / L_cc, Linv[i][c] (i > c) stored at A[c][i]
+    for (int c = tid; c < L; c += CHOL_LDS_THREADS) {
+        const double dc = 1.0 / A[c * ld + c];
+        idiag[c] = dc;
+        for (int i = c + 1; i < L; ++i) {
+            double sum = A[i * ld + c] * dc;
+            for (int k = c + 1; k < i; ++k) sum = fma(A[i * ld + k], A[c * ld + k], sum);
+            A[c * ld + i] = -sum / A[i * ld + i];
+        }
+    }
+    __syncthreads();
+    // M^-1[i][j] = sum_{k >= max(i, j)} Linv[k][i] Linv[k][j]
+    for (int idx = tid; idx < L * L; idx += CHOL_LDS_THREADS) {
+        const int i = idx / L, j = idx % L;
+        const int k0 = i > j ? i : j;
+        double sum = 0.0;
+        for (int k = k0; k < L; ++k) {
+            const double a = k == i ? idiag[i] : A[i * ld + k];
+            const double b = k == j ? idiag[j] : A[j * ld + k];
+            sum = fma(a, b, sum);
+        }
+        Minv[idx] = sum;
+    }
+    __syncthreads();
+    for (int c = tid; c < L; c += CHOL_LDS_THREADS) {
+        double sum = 0.0;
+        for (int k = 0; k < L; ++k) sum += Minv[(size_t)k * L + c];
+        mean[c] = sum / L;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < L * L; idx += CHOL_LDS_THREADS)
+        W[idx] = -(Minv[idx] - mean[idx % L]);
+}
+
+void launch_chol(const double *S, int L, double *Lf, double *Minv, double *W, int *flag,
+                 hipStream_t s) {
+    if (L <= CHOL_LDS_MAX)
+        hipLaunchKernelGGL(k_chol_lds, dim3(1), dim3(CHOL_LDS_THREADS), 0, s, S, L, Minv, W,
+                           flag);
+    else
+        hipLaunchKernelGGL(k_chol_w, dim3(1), dim3(CHOL_THREADS), 0, s, S, L, Lf, Minv, W, flag);
+}
+
 // Pt[c, :] = sum_k G[k, c] T[k, :]; one wave per column, lanes over electrodes.
 __global__ void k_gather(const int32_t *cp, const int32_t *ri, const double *gv, int n_cols,
                          const double *T, int L, double *Pt) {
@@ -278,7 +360,7 @@ zi_status zi_eit_source_impl(const zi_system *sys, const double *T, int32_t P, c
     ZI_HIP(hipMemcpyAsync(Id, I, sizeof(double) * L * P, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_schur, dim3(L), dim3(64), 0, s, sys->e_ptr, sys->e_item, sys->b_row,
                        sys->b_val, sys->C, T, L, S);
-    hipLaunchKernelGGL(k_chol_w, dim3(1), dim3(CHOL_THREADS), 0, s, S, L, Lf, Minv, W, flag);
+    launch_chol(S, L, Lf, Minv, W, flag, s);
     hipLaunchKernelGGL(k_minv_apply, dim3(grid_for((size_t)L * P, 128)), dim3(128), 0, s, Minv, Id,
                        L, P, Mi);
     hipLaunchKernelGGL(k_avg_ref, dim3(grid_for((size_t)L * P, 128)), dim3(128), 0, s, Mi, L, P, Y);
@@ -351,7 +433,7 @@ zi_status zi_leadfield_impl(const zi_system *csys, const double *T, int32_t n_co
     }
     hipLaunchKernelGGL(k_schur, dim3(L), dim3(64), 0, s, sys->e_ptr, sys->e_item, sys->b_row,
                        sys->b_val, sys->C, T, L, S);
-    hipLaunchKernelGGL(k_chol_w, dim3(1), dim3(CHOL_THREADS), 0, s, S, L, Lf, Minv, sys->W, flag);
+    launch_chol(S, L, Lf, Minv, sys->W, flag, s);
     ZI_HIP(hipGetLastError());
     if (n_cols > 0) {
         hipLaunchKernelGGL(k_gather, dim3(grid_for((size_t)n_cols * 64, 256)), dim3(256), 0, s, cp,

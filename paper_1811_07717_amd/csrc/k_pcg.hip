@@ -351,7 +351,10 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
     }
 }
 
-constexpr int UNROLL = 4;   // rows per lane per step in the streaming kernels
+// Rows per lane per step in the streaming kernels (measured best on gfx950:
+// the in-place residual update gains from more loads in flight).
+constexpr int UNROLL_U = 8;   // k_update
+constexpr int UNROLL_P = 4;   // k_pupdate
 
 // R -= alpha Q; partials r.D^-1 r and r.r of the new R.  (X is updated
 // lazily by k_xflush from the ring of the last LAZY search directions.)
@@ -372,11 +375,11 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
         al[v] = ln.ok[v] ? ld2(alpha + ln.c[v]) : make_double2(0.0, 0.0);
     }
     const int r1 = sc.re;
-    for (int base = sc.rs + sc.first + ln.slot; base - ln.slot < r1; base += UNROLL * sc.stride) {
-        double2 r[UNROLL][NV], q[UNROLL][NV];
-        double di[UNROLL];
+    for (int base = sc.rs + sc.first + ln.slot; base - ln.slot < r1; base += UNROLL_U * sc.stride) {
+        double2 r[UNROLL_U][NV], q[UNROLL_U][NV];
+        double di[UNROLL_U];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
+        for (int u = 0; u < UNROLL_U; ++u) {
             const int row = base + u * sc.stride;
             const bool rv = row < r1;
             di[u] = rv ? dinv[row] : 0.0;
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
             }
         }
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
+        for (int u = 0; u < UNROLL_U; ++u) {
             const int row = base + u * sc.stride;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -468,11 +471,11 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
     for (int v = 0; v < NV; ++v)
         be[v] = (ln.ok[v] && beta) ? ld2(beta + ln.c[v]) : make_double2(0.0, 0.0);
     const int r1 = sc.re;
-    for (int base = sc.rs + sc.first + ln.slot; base - ln.slot < r1; base += UNROLL * sc.stride) {
-        double2 r[UNROLL][NV], p[UNROLL][NV];
-        double di[UNROLL];
+    for (int base = sc.rs + sc.first + ln.slot; base - ln.slot < r1; base += UNROLL_P * sc.stride) {
+        double2 r[UNROLL_P][NV], p[UNROLL_P][NV];
+        double di[UNROLL_P];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
+        for (int u = 0; u < UNROLL_P; ++u) {
             const int row = base + u * sc.stride;
             const bool rv = row < r1;
             di[u] = rv ? dinv[row] : 0.0;
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
             }
         }
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
+        for (int u = 0; u < UNROLL_P; ++u) {
             const int row = base + u * sc.stride;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -925,6 +928,7 @@ struct SolveCtx {
     EventTimer timer{nullptr};
     // event pairs per timed kernel: spmm_pq, update, pupdate, xflush
     std::vector<hipEvent_t> ev[4];
+    int calls[4] = {0, 0, 0, 0};   // launches of the same kernels
     int it = 0;               // iterations of the block loop so far
     int flushed = 0;          // iterations whose steps are already in X
     int refinements = 0;
@@ -963,6 +967,7 @@ struct Timed {
     bool on;
     Timed(SolveCtx &c_, int w, hipStream_t s_, bool sample)
         : c(c_), which(w), s(s_), on(c_.timing && sample) {
+        ++c.calls[which];
         if (!on) return;
         hipEvent_t e0;
         if ((st = c.timer.get(&e0)) != ZI_OK || (st = c.timer.get(&e1)) != ZI_OK) return;
@@ -1286,6 +1291,7 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
                 st->kernel_name[q] = names[q];
                 st->kernel_ms[q] = ms;
                 st->kernel_launches[q] = (int32_t)(c.ev[q].size() / 2);
+                st->kernel_calls[q] = c.calls[q];
                 st->kernel_bytes[q] = bytes[q];
             }
         }

@@ -51,7 +51,7 @@ class ZiSolveStats(ctypes.Structure):
                 ("refinements", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("n_kernels", ctypes.c_int32), ("kernel_ms", ctypes.c_double * 8),
                 ("kernel_launches", ctypes.c_int32 * 8), ("kernel_bytes", ctypes.c_int64 * 8),
-                ("kernel_name", ctypes.c_char_p * 8)]
+                ("kernel_name", ctypes.c_char_p * 8), ("kernel_calls", ctypes.c_int32 * 8)]
 
 
 class ZiInfo(ctypes.Structure):
@@ -269,7 +269,8 @@ class System:
                      status=rc, kernels={})
         for k in range(st.n_kernels):
             stats["kernels"][st.kernel_name[k].decode()] = dict(
-                ms=st.kernel_ms[k], launches=st.kernel_launches[k], bytes=st.kernel_bytes[k])
+                ms=st.kernel_ms[k], launches=st.kernel_launches[k], bytes=st.kernel_bytes[k],
+                calls=st.kernel_calls[k])
         if raise_on_error:
             _check(rc, "zi_transfer_solve")
         return T, stats
