@@ -212,26 +212,52 @@ __global__ void k_gather(const int32_t *cp, const int32_t *ri, const double *gv,
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
+// Four waves per block, 16 output columns each (64 per block).  W is staged
+// in LDS GK columns at a time (rows padded to GK + 1 so that the 16 rows a
+// wave reads per MFMA fall in different banks); every wave forms all MT row
+// tiles of its columns from the staged chunk, so W is read once per 64 output
+// columns and the B operand once per k step.
+constexpr int GEMM_THREADS = 256;
+constexpr int GK = 16;
+
+template <int MT, class F>
+__device__ __forceinline__ void gemm_tile(const double *W, const double *Pt, int L, int n_cols,
+                                          double (*Ws)[GK + 1], F mfma_step) {
+    const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + wv * 16 + (t & 15);
+    const int kq = t >> 4;
+    for (int k0 = 0; k0 < L; k0 += GK) {
+        __syncthreads();   // previous chunk consumed
+        for (int idx = threadIdx.x; idx < MT * 16 * GK; idx += GEMM_THREADS) {
+            const int r = idx / GK, kk = idx % GK;
+            Ws[r][kk] = (r < L && k0 + kk < L) ? W[(size_t)r * L + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; kk += 4) {
+            const int k = k0 + kk + kq;
+            const double b = (col < n_cols && k < L) ? Pt[(size_t)col * L + k] : 0.0;
+            mfma_step(kk + kq, b);
+        }
+    }
+}
+
 template <int MT>
-__global__ __launch_bounds__(64) void k_gemm_f64(const double *W, const double *Pt, int L,
-                                                 int n_cols, double *LF) {
-    const int t = threadIdx.x;
-    const int c0 = blockIdx.x * 16;
-    const int col = c0 + (t & 15);
+__global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f64(const double *W, const double *Pt,
+                                                           int L, int n_cols, double *LF) {
+    __shared__ double Ws[MT * 16][GK + 1];
+    const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + wv * 16 + (t & 15);
     const int kq = t >> 4;
     dbl4 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < L; k0 += 4) {
-        const int k = k0 + kq;
-        const double b = (col < n_cols && k < L) ? Pt[(size_t)col * L + k] : 0.0;
+    gemm_tile<MT>(W, Pt, L, n_cols, Ws, [&](int kk, double b) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const int row = m * 16 + (t & 15);
-            const double a = (row < L && k < L) ? W[(size_t)row * L + k] : 0.0;
-            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
-        }
-    }
+        for (int m = 0; m < MT; ++m)
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[m * 16 + (t & 15)][kk], b, acc[m],
+                                                          0, 0, 0);
+    });
     if (col >= n_cols) return;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -243,31 +269,27 @@ __global__ __launch_bounds__(64) void k_gemm_f64(const double *W, const double *
 }
 
 template <int MT>
-__global__ __launch_bounds__(64) void k_gemm_f32(const double *W, const double *Pt, int L,
-                                                 int n_cols, double *LF) {
-    const int t = threadIdx.x;
-    const int c0 = blockIdx.x * 16;
-    const int col = c0 + (t & 15);
+__global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f32(const double *W, const double *Pt,
+                                                           int L, int n_cols, double *LF) {
+    __shared__ double Ws[MT * 16][GK + 1];
+    const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + wv * 16 + (t & 15);
     const int kq = t >> 4;
     flt4 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = flt4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < L; k0 += 4) {
-        const int k = k0 + kq;
-        const float b = (col < n_cols && k < L) ? (float)Pt[(size_t)col * L + k] : 0.f;
+    gemm_tile<MT>(W, Pt, L, n_cols, Ws, [&](int kk, double b) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const int row = m * 16 + (t & 15);
-            const float a = (row < L && k < L) ? (float)W[(size_t)row * L + k] : 0.f;
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[m], 0, 0, 0);
-        }
-    }
+        for (int m = 0; m < MT; ++m)
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)Ws[m * 16 + (t & 15)][kk],
+                                                          (float)b, acc[m], 0, 0, 0);
+    });
     if (col >= n_cols) return;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int row = m * 16 + 4 * kq + i;
+            const int row = m * 16 + 4 * kq + i;   // f32 result layout
             if (row < L) LF[(size_t)row * n_cols + col] = (double)acc[m][i];
         }
 }
@@ -439,7 +461,7 @@ zi_status zi_leadfield_impl(const zi_system *csys, const double *T, int32_t n_co
         hipLaunchKernelGGL(k_gather, dim3(grid_for((size_t)n_cols * 64, 256)), dim3(256), 0, s, cp,
                            ri, gv, n_cols, T, L, sys->Pt);
         const int mt = (L + 15) / 16;
-        const dim3 grid(grid_for(n_cols, 16)), block(64);
+        const dim3 grid(grid_for(n_cols, 64)), block(GEMM_THREADS);
         if (precision == 0) {
             ZI_GEMM_SWITCH(k_gemm_f64, mt, grid, block, 0, s, sys->W, sys->Pt, L, n_cols, LF);
         } else {
