@@ -1,0 +1,36 @@
+"""Counter calibration of paper_1811_07717_amd.counters on a synthetic
+rocprofv3 counter file: bytes = FETCH_SIZE x (true read / counted read of the
+copy) + WRITE_SIZE x (true write / counted write of the copy)."""
+import csv
+
+from paper_1811_07717_amd import counters
+
+HEAD = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def _write(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(HEAD)
+        for i, (name, val) in enumerate(rows):
+            w.writerow([i, name, "X", val])
+
+
+def test_calibration_and_traffic_file(tmp_path):
+    spmm = "void (anonymous namespace)::k_spmm<32, 2, double, double, true>(Geom, ...)"
+    upd = "void (anonymous namespace)::k_update<32, 2, double>(Geom, ...)"
+    copy = "zi::(anonymous namespace)::k_copy2(double2 const*, double2*, unsigned long)"
+    # the copy moves 1 MiB each way; FETCH counts half of it, WRITE all of it
+    _write(tmp_path / "f.csv", [(copy, 512.0), (spmm, 100.0), (spmm, 300.0), (upd, 50.0)])
+    _write(tmp_path / "w.csv", [(copy, 1024.0), (spmm, 10.0), (spmm, 30.0), (upd, 5.0)])
+    res, ff, wf = counters.summarize(tmp_path / "f.csv", tmp_path / "w.csv", copy_mib=1.0)
+    assert ff == 2.0 and wf == 1.0
+    assert res["spmm_pq"]["launches"] == 2
+    assert res["spmm_pq"]["bytes_per_launch"] == int((200.0 * 2 + 20.0) * 1024)
+    assert res["update"]["bytes_per_launch"] == int((50.0 * 2 + 5.0) * 1024)
+    assert "copy" not in res
+
+
+def test_source_hash_is_stable():
+    assert counters.source_hash() == counters.source_hash()
+    assert len(counters.source_hash()) == 16
