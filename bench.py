@@ -77,23 +77,29 @@ def copy_bandwidth(torch, dev, mib=2048):
 
 
 def cpu_baseline(H, L):
-    """Oracle (plain NumPy/SciPy FP64) on a bounded sample of the workload:
-    full assembly plus the PCG of one electrode column, extrapolated to the
-    L columns of one lead-field build."""
+    """Oracle (plain NumPy/SciPy FP64, one thread) on a bounded sample of the
+    workload: full assembly plus the PCG of three electrode columns (first,
+    middle, last), extrapolated to the L columns of one lead-field build."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import fem, solve
-    t0 = time.perf_counter()
-    S = fem.assemble(H.nodes, H.tets, H.sigma, H.tris, H.tri_electrode, H.Z)
-    t_asm = time.perf_counter() - t0
-    d = fem.preconditioner_diag(S["A"])
-    b = S["B"][:, [0]].toarray().ravel()
-    t0 = time.perf_counter()
-    _, its, _ = solve.pcg(S["A"], b, d, tol=1e-8)
-    t_col = time.perf_counter() - t0
+    cols = sorted({0, L // 2, L - 1})
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        S = fem.assemble(H.nodes, H.tets, H.sigma, H.tris, H.tri_electrode, H.Z)
+        t_asm = time.perf_counter() - t0
+        d = fem.preconditioner_diag(S["A"])
+        its = []
+        t0 = time.perf_counter()
+        for c in cols:
+            b = S["B"][:, [c]].toarray().ravel()
+            its.append(solve.pcg(S["A"], b, d, tol=1e-8)[1])
+        t_col = (time.perf_counter() - t0) / len(cols)
     t_step = t_asm + L * t_col
     return {"value": L / t_step, "unit": "electrode-solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle assembly of the full mesh ({t_asm:.1f} s) + PCG of electrode "
-                       f"column 0 to 1e-8 ({its} it, {t_col:.1f} s), extrapolated to {L} "
-                       f"columns; single-threaded NumPy/SciPy")}
+            "sample": (f"oracle assembly of the full mesh ({t_asm:.1f} s) + PCG to 1e-8 of "
+                       f"electrode columns {cols} ({its} iterations, {t_col:.1f} s per column), "
+                       f"extrapolated to {L} columns; NumPy/SciPy limited to one thread")}
 
 
 def main():
