@@ -352,18 +352,20 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
 }
 
 // Rows per lane per step in the streaming kernels (measured best on gfx950:
-// the in-place residual update gains from more loads in flight).
-constexpr int UNROLL_U = 8;   // k_update
-constexpr int UNROLL_P = 4;   // k_pupdate
+// the residual update of FP64 vectors gains from more loads in flight).
+template <class TP>
+constexpr int unroll_update() { return sizeof(TP) == 8 ? 8 : 4; }   // k_update
+constexpr int UNROLL_P = 4;                                           // k_pupdate
 
 // R -= alpha Q; partials r.D^-1 r and r.r of the new R.  (X is updated
 // lazily by k_xflush from the ring of the last LAZY search directions.)
 template <int LPR, int NV, class TP>
 __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restrict__ alpha,
                                                   const double *__restrict__ dinv,
-                                                  double *__restrict__ R,
+                                                  TP *__restrict__ R,
                                                   const TP *__restrict__ Q, double *prz,
                                                   double *prr) {
+    constexpr int UR = unroll_update<TP>();
     Sched sc;
     if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
     Lane<LPR, NV> ln(g, sc.cc);
@@ -375,11 +377,11 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
         al[v] = ln.ok[v] ? ld2(alpha + ln.c[v]) : make_double2(0.0, 0.0);
     }
     const int r1 = sc.re;
-    for (int base = sc.rs + sc.first + ln.slot; base - ln.slot < r1; base += UNROLL_U * sc.stride) {
-        double2 r[UNROLL_U][NV], q[UNROLL_U][NV];
-        double di[UNROLL_U];
+    for (int base = sc.rs + sc.first + ln.slot; base - ln.slot < r1; base += UR * sc.stride) {
+        double2 r[UR][NV], q[UR][NV];
+        double di[UR];
 #pragma unroll
-        for (int u = 0; u < UNROLL_U; ++u) {
+        for (int u = 0; u < UR; ++u) {
             const int row = base + u * sc.stride;
             const bool rv = row < r1;
             di[u] = rv ? dinv[row] : 0.0;
@@ -392,7 +394,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
             }
         }
 #pragma unroll
-        for (int u = 0; u < UNROLL_U; ++u) {
+        for (int u = 0; u < UR; ++u) {
             const int row = base + u * sc.stride;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -400,6 +402,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
                 double2 rr = r[u][v];
                 rr.x = fma(-al[v].x, q[u][v].x, rr.x);
                 rr.y = fma(-al[v].y, q[u][v].y, rr.y);
+                rr = as_stored(rr, (const TP *)R);   // the dots see r as stored
                 stn2(R + (size_t)row * g.ldp + ln.c[v], rr);
                 acc[0][v].x = fma(rr.x, rr.x * di[u], acc[0][v].x);
                 acc[0][v].y = fma(rr.y, rr.y * di[u], acc[0][v].y);
@@ -460,7 +463,7 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
 template <int LPR, int NV, class TP>
 __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restrict__ beta,
                                                    const double *__restrict__ dinv,
-                                                   const double *__restrict__ R,
+                                                   const TP *__restrict__ R,
                                                    const TP *__restrict__ P,
                                                    TP *__restrict__ Pout) {
     Sched sc;
@@ -509,7 +512,7 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
 // R = B - Q (Q may be null: R = B).  Partials: b.b, r.D^-1 r, r.r.  R may be
 // null (only the partials are wanted: true residual).  Solver row r takes the
 // right-hand side of node perm[r].
-template <int LPR, int NV>
+template <int LPR, int NV, class TR>
 __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ bp,
                                                     const int32_t *__restrict__ bc,
@@ -517,7 +520,7 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__res
                                                     const int32_t *__restrict__ colmap,
                                                     const double *__restrict__ dinv,
                                                     const double *__restrict__ Q,
-                                                    double *__restrict__ R, double *pbb,
+                                                    TR *__restrict__ R, double *pbb,
                                                     double *prz, double *prr) {
     Sched sc;
     if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
@@ -547,7 +550,10 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__res
                 r.x = b.x - q.x;
                 r.y = b.y - q.y;
             }
-            if (R) st2(R + o, r);
+            if (R) {
+                r = as_stored(r, (const TR *)R);   // the dots see r as stored
+                st2(R + o, r);
+            }
             acc[0][v].x = fma(b.x, b.x, acc[0][v].x);
             acc[0][v].y = fma(b.y, b.y, acc[0][v].y);
             acc[1][v].x = fma(r.x, r.x * di, acc[1][v].x);
@@ -781,14 +787,14 @@ void launch_spmm(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t 
 
 template <int LPR, int NV, class TP>
 void launch_update(const Geom &g, hipStream_t s, const double *alpha, const double *dinv,
-                   double *R, const TP *Q, double *prz, double *prr) {
+                   TP *R, const TP *Q, double *prz, double *prr) {
     hipLaunchKernelGGL((k_update<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, alpha, dinv,
                        R, Q, prz, prr);
 }
 
 template <int LPR, int NV, class TP>
 void launch_pupdate(const Geom &g, hipStream_t s, const double *beta, const double *dinv,
-                    const double *R, const TP *P, TP *Pout) {
+                    const TP *R, const TP *P, TP *Pout) {
     hipLaunchKernelGGL((k_pupdate<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, beta, dinv,
                        R, P, Pout);
 }
@@ -800,11 +806,11 @@ void launch_xflush(const Geom &g, hipStream_t s, int cnt, const double *alphas, 
                        ring, X);
 }
 
-template <int LPR, int NV>
+template <int LPR, int NV, class TR>
 void launch_residual(const Geom &g, hipStream_t s, const zi_system *sys, const int32_t *colmap,
-                     const double *dinv, const double *Q, double *R, double *pbb, double *prz,
+                     const double *dinv, const double *Q, TR *R, double *pbb, double *prz,
                      double *prr) {
-    hipLaunchKernelGGL((k_residual<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, sys->perm,
+    hipLaunchKernelGGL((k_residual<LPR, NV, TR>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, sys->perm,
                        sys->b_ptr, sys->b_col, sys->b_val, colmap, dinv, Q, R, pbb, prz, prr);
 }
 
@@ -1038,7 +1044,7 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
         Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
         ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)al, (const double *)ws->dinv,
-                       ws->R, (const TP *)Q, ws->part[1], ws->part[2]);
+                       reinterpret_cast<TP *>(ws->R), (const TP *)Q, ws->part[1], ws->part[2]);
     }
     if ((k + 1) % LAZY == 0 || replace_r) ZI_TRY(enqueue_flush<TP>(c, k + 1, s));
     if (replace_r) ZI_TRY(true_residual(c, s, true));
@@ -1048,7 +1054,7 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
         Timed t(c, 2, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
         ZI_TILE_SWITCH(tile, launch_pupdate, g, s, (const double *)c.sc.beta,
-                       (const double *)ws->dinv, (const double *)ws->R, (const TP *)Pk, Pn);
+                       (const double *)ws->dinv, (const TP *)ws->R, (const TP *)Pk, Pn);
     }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
@@ -1080,9 +1086,15 @@ zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r) {
     zi_solver_ws *ws = c.ws;
     ZI_TILE_SWITCH(c.tile, launch_spmm, c.g, s, c.sys->sp_ptr, c.sys->sp_col,
                    (const double *)c.sys->sp_val, (const double *)ws->X, ws->Q, (double *)nullptr);
-    ZI_TILE_SWITCH(c.tile, launch_residual, c.g, s, c.sys, (const int32_t *)c.colmap, ws->dinv,
-                   ws->Q, write_r ? ws->R : (double *)nullptr, ws->part[0], ws->part[1],
-                   ws->part[2]);
+    if (c.mixed) {   // R holds float32 in the mixed mode
+        ZI_TILE_SWITCH(c.tile, launch_residual, c.g, s, c.sys, (const int32_t *)c.colmap,
+                       ws->dinv, ws->Q, write_r ? reinterpret_cast<float *>(ws->R) : nullptr,
+                       ws->part[0], ws->part[1], ws->part[2]);
+    } else {
+        ZI_TILE_SWITCH(c.tile, launch_residual, c.g, s, c.sys, (const int32_t *)c.colmap,
+                       ws->dinv, ws->Q, write_r ? ws->R : nullptr, ws->part[0], ws->part[1],
+                       ws->part[2]);
+    }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
 }
@@ -1092,7 +1104,7 @@ zi_status enqueue_restart_direction(SolveCtx &c, hipStream_t s) {
     if (c.mixed) {
         float *p = c.P<float>(c.it);
         ZI_TILE_SWITCH(c.tile, launch_pupdate, c.g, s, (const double *)nullptr,
-                       (const double *)c.ws->dinv, (const double *)c.ws->R, (const float *)p, p);
+                       (const double *)c.ws->dinv, (const float *)c.ws->R, (const float *)p, p);
     } else {
         double *p = c.P<double>(c.it);
         ZI_TILE_SWITCH(c.tile, launch_pupdate, c.g, s, (const double *)nullptr,
@@ -1191,8 +1203,15 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
         ZI_TRY(gather_rows(o->x0, L, sys->perm, ws->X, ldp, n, L, s));
         ZI_TRY(true_residual(c, s, true));
     } else {
-        ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, (const int32_t *)c.colmap, ws->dinv,
-                       (const double *)nullptr, ws->R, ws->part[0], ws->part[1], ws->part[2]);
+        if (c.mixed) {
+            ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, (const int32_t *)c.colmap,
+                           ws->dinv, (const double *)nullptr, reinterpret_cast<float *>(ws->R),
+                           ws->part[0], ws->part[1], ws->part[2]);
+        } else {
+            ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, (const int32_t *)c.colmap,
+                           ws->dinv, (const double *)nullptr, ws->R, ws->part[0], ws->part[1],
+                           ws->part[2]);
+        }
     }
     hipLaunchKernelGGL(k_red_init, dim3(ldp), dim3(RED), 0, s, sc, ws->part[0], ws->part[1],
                        ws->part[2], c.g.nrt, L, c.tol2, c.eta2);
@@ -1271,14 +1290,14 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
         st->tile = c.tile;
         st->n_kernels = 0;
         if (c.timing) {
-            const int64_t pe = c.mixed ? 4 : 8;   // bytes of a P or Q entry
+            const int64_t pe = c.mixed ? 4 : 8;   // bytes of a P, Q or R entry
             const int64_t ne = (int64_t)n * ldp;
             const int64_t abytes = (int64_t)c.sys->sp_nnz * 12 + (int64_t)(n + 1) * 4;
             static const char *names[4] = {"spmm_pq", "update", "pupdate", "xflush"};
             const int64_t bytes[4] = {
                 abytes + 2 * pe * ne,                      // read P, write Q
-                (16 + pe) * ne + (int64_t)n * 8,           // r/w R, read Q, D^-1
-                (8 + 2 * pe) * ne + (int64_t)n * 8,        // read R, P; write P; D^-1
+                3 * pe * ne + (int64_t)n * 8,              // r/w R, read Q, D^-1
+                3 * pe * ne + (int64_t)n * 8,              // read R, P; write P; D^-1
                 (16 + LAZY * pe) * ne};                    // r/w X, read LAZY directions
             st->n_kernels = 4;
             for (int q = 0; q < 4; ++q) {
