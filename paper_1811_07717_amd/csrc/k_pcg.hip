@@ -96,6 +96,7 @@ struct Lane {
     static constexpr int RSTEP = WAVES * RPW;
     int w, r, lr, slot;
     int c[NV];
+    int cs[NV];   // c clamped into the padded columns (safe load address)
     bool ok[NV];
     __device__ __forceinline__ Lane(const Geom &g, int cc) {
         const int tid = threadIdx.x;
@@ -108,6 +109,7 @@ struct Lane {
         for (int v = 0; v < NV; ++v) {
             c[v] = cc * CW + 2 * (lr + LPR * v);
             ok[v] = c[v] < g.ldp;
+            cs[v] = ok[v] ? c[v] : 0;
         }
     }
 };
@@ -357,6 +359,15 @@ template <class TP>
 constexpr int unroll_update() { return sizeof(TP) == 8 ? 8 : 4; }   // k_update
 constexpr int UNROLL_P = 4;                                           // k_pupdate
 
+// Load form of the streaming kernels.  FP32 vectors are loaded without a
+// guard, from addresses clamped into the block's rows and the padded columns,
+// and out-of-range entries are masked afterwards: a guarded load that widens
+// to double waits for its own data inside the guard, so only one or two loads
+// per wave would be in flight.  FP64 vectors keep the guarded form, which
+// measures faster for them.
+template <class TP>
+constexpr bool clamp_loads() { return sizeof(TP) == 4; }
+
 // R -= alpha Q; partials r.D^-1 r and r.r of the new R.  (X is updated
 // lazily by k_xflush from the ring of the last LAZY search directions.)
 template <int LPR, int NV, class TP>
@@ -366,6 +377,7 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
                                                   const TP *__restrict__ Q, double *prz,
                                                   double *prr) {
     constexpr int UR = unroll_update<TP>();
+    constexpr bool CL = clamp_loads<TP>();
     Sched sc;
     if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
     Lane<LPR, NV> ln(g, sc.cc);
@@ -383,12 +395,13 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
 #pragma unroll
         for (int u = 0; u < UR; ++u) {
             const int row = base + u * sc.stride;
-            const bool rv = row < r1;
-            di[u] = rv ? dinv[row] : 0.0;
+            const bool rv = CL || row < r1;
+            const int rl = CL ? min(row, r1 - 1) : row;
+            di[u] = rv ? dinv[rl] : 0.0;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const size_t o = (size_t)row * g.ldp + ln.c[v];
-                const bool on = rv && ln.ok[v];
+                const size_t o = (size_t)rl * g.ldp + (CL ? ln.cs[v] : ln.c[v]);
+                const bool on = CL || (rv && ln.ok[v]);
                 r[u][v] = on ? ldn2(R + o) : make_double2(0.0, 0.0);
                 q[u][v] = on ? ldn2(Q + o) : make_double2(0.0, 0.0);
             }
@@ -436,16 +449,23 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
         for (int v = 0; v < NV; ++v)
             al[j][v] = (j < cnt && ln.ok[v]) ? ld2(alphas + (size_t)j * g.ldp + ln.c[v])
                                              : make_double2(0.0, 0.0);
+    // FP32 rings: unconditional loads from clamped addresses (slots past cnt
+    // read slot 0, cnt >= 1), masked at the store, as in k_update.
+    constexpr bool CL = clamp_loads<TP>();
+    __builtin_assume(cnt >= 1);   // the host launches no empty flush
     for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
         const int row = base + ln.slot;
-        if (row >= sc.re) continue;
+        if (!CL && row >= sc.re) continue;
+        const int rl = CL ? min(row, sc.re - 1) : row;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            if (!ln.ok[v]) continue;
-            const size_t o = (size_t)row * g.ldp + ln.c[v];
+            if (!CL && !ln.ok[v]) continue;
+            const size_t o = (size_t)rl * g.ldp + (CL ? ln.cs[v] : ln.c[v]);
             double2 p[LAZY];
 #pragma unroll
-            for (int j = 0; j < LAZY; ++j) p[j] = j < cnt ? ldn2(ring.p[j] + o) : make_double2(0.0, 0.0);
+            for (int j = 0; j < LAZY; ++j)
+                p[j] = CL ? ldn2(ring.p[j < cnt ? j : 0] + o)
+                          : (j < cnt ? ldn2(ring.p[j] + o) : make_double2(0.0, 0.0));
             double2 x = ldn2(X + o);
 #pragma unroll
             for (int j = 0; j < LAZY; ++j) {
@@ -454,7 +474,7 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
                     x.y = fma(al[j][v].y, p[j].y, x.y);
                 }
             }
-            stn2(X + o, x);
+            if (!CL || (row < sc.re && ln.ok[v])) stn2(X + o, x);
         }
     }
 }
@@ -466,6 +486,7 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
                                                    const TP *__restrict__ R,
                                                    const TP *__restrict__ P,
                                                    TP *__restrict__ Pout) {
+    constexpr bool CL = clamp_loads<TP>();
     Sched sc;
     if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
     Lane<LPR, NV> ln(g, sc.cc);
@@ -480,12 +501,13 @@ __global__ __launch_bounds__(BLOCK) void k_pupdate(Geom g, const double *__restr
 #pragma unroll
         for (int u = 0; u < UNROLL_P; ++u) {
             const int row = base + u * sc.stride;
-            const bool rv = row < r1;
-            di[u] = rv ? dinv[row] : 0.0;
+            const bool rv = CL || row < r1;
+            const int rl = CL ? min(row, r1 - 1) : row;
+            di[u] = rv ? dinv[rl] : 0.0;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const size_t o = (size_t)row * g.ldp + ln.c[v];
-                const bool on = rv && ln.ok[v];
+                const size_t o = (size_t)rl * g.ldp + (CL ? ln.cs[v] : ln.c[v]);
+                const bool on = CL || (rv && ln.ok[v]);
                 r[u][v] = on ? ldn2(R + o) : make_double2(0.0, 0.0);
                 p[u][v] = (on && beta) ? ldn2(P + o) : make_double2(0.0, 0.0);
             }
