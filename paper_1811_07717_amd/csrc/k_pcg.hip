@@ -134,8 +134,10 @@ __device__ __forceinline__ void st2(float *p, double2 v) {
 // touches once: each block vector is far larger than L2 and the Infinity
 // Cache, and keeping it out of them leaves room for the SpMM's gathers.  Two
 // adjacent scalar accesses become one 16-byte (8-byte) memory instruction.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 ldn2(const double *p) {
-    return make_double2(__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1));
+    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(p));
+    return make_double2(v.x, v.y);
 }
 __device__ __forceinline__ double2 ldn2(const float *p) {
     return make_double2((double)__builtin_nontemporal_load(p),
