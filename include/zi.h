@@ -93,6 +93,17 @@ enum { ZI_FP64 = 0,         /* all arithmetic in float64 */
                                and columns whose true residual misses tol at the
                                end restart (float64 iterative refinement) */ };
 
+/* Form of the PCG iteration (Sec. 2.3.1 solves with Jacobi-preconditioned
+ * CG; both forms give the same iterates in exact arithmetic). */
+enum { ZI_PCG_AUTO = 0,       /* single-reduction in ZI_FP64, classic in
+                                 ZI_FP32_SPMM_IR */
+       ZI_PCG_CLASSIC = 1,    /* two reductions per iteration (p.Ap, then
+                                 r.D^-1 r); every search direction is formed */
+       ZI_PCG_SINGLE = 2      /* single-reduction form of Chronopoulos and Gear:
+                                 s = A D^-1 r + beta s by recurrence, the search
+                                 directions are formed lazily beside x every 8
+                                 iterations; ZI_FP64 only */ };
+
 /* Options of zi_transfer_solve.  Zero-initialised fields take defaults. */
 typedef struct {
     double tol;          /* relative residual ||b - A t|| / ||b|| target;
@@ -112,6 +123,8 @@ typedef struct {
                                columns (distinct, in [0, L)); T, x0 and the
                                statistics then have n_columns columns */
     int32_t n_columns;
+    int32_t form;        /* ZI_PCG_AUTO, ZI_PCG_CLASSIC or ZI_PCG_SINGLE
+                            (ZI_PCG_SINGLE with ZI_FP32_SPMM_IR: ZI_EINVAL) */
 } zi_solve_opts;
 
 /* Statistics of zi_transfer_solve.  The HOST arrays are caller-owned, length
@@ -168,10 +181,11 @@ zi_status zi_transfer_solve_batch(zi_system *const *systems, int32_t n_systems,
                                   const zi_solve_opts *opts, double *const *T,
                                   zi_solve_stats *stats, void *hip_stream);
 
-/* Autotuner: times the solver's SpMM (with its p.q epilogue) for every tile
- * on this system's n x L block in the given precision (ZI_FP64 or
- * ZI_FP32_SPMM_IR) and stores the fastest; later solves with tile = -1 use
- * it.  best_tile (HOST, may be NULL) receives it; ms (HOST, may be NULL,
+/* Autotuner: times the solver's SpMM for every tile on this system's n x L
+ * block in the given precision and stores the fastest; later solves with
+ * tile = -1 use it.  ZI_FP64 times the single-reduction SpMM (S = A D^-1 R +
+ * beta S with its delta epilogue), ZI_FP32_SPMM_IR the classic one (Q = A P
+ * with its p.q epilogue).  best_tile (HOST, may be NULL) receives it; ms (HOST, may be NULL,
  * zi_tile_count() entries) the measured milliseconds per tile. */
 zi_status zi_autotune(zi_system *sys, int32_t precision, int32_t *best_tile, double *ms,
                       void *hip_stream);

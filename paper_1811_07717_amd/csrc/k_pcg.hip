@@ -355,6 +355,60 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
     }
 }
 
+// SpMM of the single-reduction PCG (FP64): W = A D^-1 R through the values
+// vs = a_ij / d_j, then S = W + beta S in place, and the partials of
+// delta = sum_i (D^-1 R)[i,c] W[i,c] (R of the own row comes from the gather
+// of the diagonal entry).  beta == nullptr: S = W.
+template <int LPR, int NV>
+__global__ __launch_bounds__(BLOCK) void k_spmm_sr(Geom g, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const double *__restrict__ vs,
+                                                   const double *__restrict__ dinv,
+                                                   const double *__restrict__ R,
+                                                   const double *__restrict__ beta,
+                                                   double *__restrict__ S, double *part) {
+    Sched sc;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
+    Lane<LPR, NV> ln(g, sc.cc);
+    double2 be[NV];
+    double2 dotacc[1][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        be[v] = (ln.ok[v] && beta) ? ld2(beta + ln.c[v]) : make_double2(0.0, 0.0);
+        dotacc[0][v] = make_double2(0.0, 0.0);
+    }
+    for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
+        const int row = base + ln.slot;
+        if (row >= sc.re) continue;
+        // the row's S entries are requested before the gathers
+        double2 so[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            so[v] = (ln.ok[v] && beta) ? ldn2(S + (size_t)row * g.ldp + ln.c[v])
+                                       : make_double2(0.0, 0.0);
+        const double di = dinv[row];
+        double2 acc[NV], xs[NV];
+        bool self;
+        row_product<LPR, NV, double, double>(rp, ci, vs, R, g.ldp, row, ln.lr, ln.c, ln.ok, acc,
+                                             xs, self);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (!ln.ok[v]) continue;
+            const size_t o = (size_t)row * g.ldp + ln.c[v];
+            double2 sn;
+            sn.x = fma(be[v].x, so[v].x, acc[v].x);
+            sn.y = fma(be[v].y, so[v].y, acc[v].y);
+            stn2(S + o, sn);
+            double2 xr = xs[v];
+            if (!self) xr = ld2(R + o);
+            dotacc[0][v].x = fma(xr.x * di, acc[v].x, dotacc[0][v].x);
+            dotacc[0][v].y = fma(xr.y * di, acc[v].y, dotacc[0][v].y);
+        }
+    }
+    double *const parts[1] = {part};
+    block_partials<LPR, NV, 1>(g, ln, sc.cc, sc.prow, dotacc, parts);
+}
+
 // Rows per lane per step in the streaming kernels (measured best on gfx950:
 // the residual update of FP64 vectors gains from more loads in flight).
 template <class TP>
@@ -370,14 +424,15 @@ constexpr int UNROLL_P = 4;                                           // k_pupda
 template <class TP>
 constexpr bool clamp_loads() { return sizeof(TP) == 4; }
 
-// R -= alpha Q; partials r.D^-1 r and r.r of the new R.  (X is updated
-// lazily by k_xflush from the ring of the last LAZY search directions.)
+// Rout = R - alpha Q (Rout == R: in place); partials r.D^-1 r and r.r of
+// the new residual.  (X is updated lazily from the ring of the last LAZY
+// search directions.)  Each entry is read and written by the same lane, so
+// the in-place form is safe.
 template <int LPR, int NV, class TP>
 __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restrict__ alpha,
                                                   const double *__restrict__ dinv,
-                                                  TP *__restrict__ R,
-                                                  const TP *__restrict__ Q, double *prz,
-                                                  double *prr) {
+                                                  const TP *R, const TP *__restrict__ Q,
+                                                  TP *Rout, double *prz, double *prr) {
     constexpr int UR = unroll_update<TP>();
     constexpr bool CL = clamp_loads<TP>();
     Sched sc;
@@ -417,8 +472,8 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
                 double2 rr = r[u][v];
                 rr.x = fma(-al[v].x, q[u][v].x, rr.x);
                 rr.y = fma(-al[v].y, q[u][v].y, rr.y);
-                rr = as_stored(rr, (const TP *)R);   // the dots see r as stored
-                stn2(R + (size_t)row * g.ldp + ln.c[v], rr);
+                rr = as_stored(rr, R);   // the dots see r as stored
+                stn2(Rout + (size_t)row * g.ldp + ln.c[v], rr);
                 acc[0][v].x = fma(rr.x, rr.x * di[u], acc[0][v].x);
                 acc[0][v].y = fma(rr.y, rr.y * di[u], acc[0][v].y);
                 acc[1][v].x = fma(rr.x, rr.x, acc[1][v].x);
@@ -477,6 +532,57 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
                 }
             }
             if (!CL || (row < sc.re && ln.ok[v])) stn2(X + o, x);
+        }
+    }
+}
+
+// Lazy search directions of the single-reduction PCG (FP64): for the
+// iterations j < cnt of the window, in order, P = D^-1 R_j + beta_j P and
+// X += alpha_j P, with the same fused multiply-adds as the direction update
+// and the X flush of the classic form; one pass over P and X per window.
+template <int LPR, int NV>
+__global__ __launch_bounds__(BLOCK) void k_pflush(Geom g, int cnt, const double *__restrict__ alphas,
+                                                  const double *__restrict__ betas,
+                                                  Ring<double> ring,
+                                                  const double *__restrict__ dinv,
+                                                  double *__restrict__ P,
+                                                  double *__restrict__ X) {
+    Sched sc;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
+    Lane<LPR, NV> ln(g, sc.cc);
+    double2 al[LAZY][NV], bt[LAZY][NV];
+#pragma unroll
+    for (int j = 0; j < LAZY; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const bool on = j < cnt && ln.ok[v];
+            al[j][v] = on ? ld2(alphas + (size_t)j * g.ldp + ln.c[v]) : make_double2(0.0, 0.0);
+            bt[j][v] = on ? ld2(betas + (size_t)j * g.ldp + ln.c[v]) : make_double2(0.0, 0.0);
+        }
+    for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
+        const int row = base + ln.slot;
+        if (row >= sc.re) continue;
+        const double di = dinv[row];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (!ln.ok[v]) continue;
+            const size_t o = (size_t)row * g.ldp + ln.c[v];
+            double2 r[LAZY];
+#pragma unroll
+            for (int j = 0; j < LAZY; ++j) r[j] = j < cnt ? ldn2(ring.p[j] + o) : make_double2(0.0, 0.0);
+            double2 p = ldn2(P + o);
+            double2 x = ldn2(X + o);
+#pragma unroll
+            for (int j = 0; j < LAZY; ++j) {
+                if (j < cnt) {
+                    p.x = fma(bt[j][v].x, p.x, r[j].x * di);
+                    p.y = fma(bt[j][v].y, p.y, r[j].y * di);
+                    x.x = fma(al[j][v].x, p.x, x.x);
+                    x.y = fma(al[j][v].y, p.y, x.y);
+                }
+            }
+            stn2(P + o, p);
+            stn2(X + o, x);
         }
     }
 }
@@ -660,8 +766,35 @@ __global__ __launch_bounds__(RED) void k_red_alpha(Scal sc, double *alpha, const
     }
 }
 
+// Step length of the single-reduction form: with gamma = r.D^-1 r (rho) and
+// delta = (D^-1 r).A(D^-1 r), p.Ap = delta - beta gamma / alpha_prev, so
+// alpha = gamma / (delta - beta gamma / alpha_prev) (= gamma / delta when
+// beta = 0).  sc.alpha keeps alpha_prev.
+__global__ __launch_bounds__(RED) void k_red_alpha_sr(Scal sc, double *alpha, const double *pdelta,
+                                                      int nrt) {
+    const int c = blockIdx.x;
+    const double delta = col_sum(pdelta, nrt, c);
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        if (sc.active[c]) {
+            const double b = sc.beta[c], gam = sc.rho[c];
+            const double pap = b == 0.0 ? delta : delta - b * gam / sc.alpha[c];
+            if (pap > 0.0) {
+                a = gam / pap;
+            } else {
+                sc.active[c] = 0;
+                sc.flag[0] = 1;
+            }
+        }
+        alpha[c] = a;
+        sc.alpha[c] = a;
+    }
+}
+
+// beta = rz / rho of the new residual; bslot (optional) keeps a copy in the
+// ring of step coefficients.
 __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, const double *prr,
-                                                  int nrt) {
+                                                  int nrt, double *bslot) {
     const int c = blockIdx.x;
     const double rz = col_sum(prz, nrt, c);
     const double rr = col_sum(prr, nrt, c);
@@ -678,6 +811,7 @@ __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, co
             }
         }
         sc.beta[c] = b;
+        if (bslot) bslot[c] = b;
     }
 }
 
@@ -811,9 +945,25 @@ void launch_spmm(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t 
 
 template <int LPR, int NV, class TP>
 void launch_update(const Geom &g, hipStream_t s, const double *alpha, const double *dinv,
-                   TP *R, const TP *Q, double *prz, double *prr) {
+                   const TP *R, const TP *Q, TP *Rout, double *prz, double *prr) {
     hipLaunchKernelGGL((k_update<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, alpha, dinv,
-                       R, Q, prz, prr);
+                       R, Q, Rout, prz, prr);
+}
+
+template <int LPR, int NV>
+void launch_spmm_sr(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t *ci,
+                    const double *vs, const double *dinv, const double *R, const double *beta,
+                    double *S, double *part) {
+    hipLaunchKernelGGL((k_spmm_sr<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, rp, ci, vs,
+                       dinv, R, beta, S, part);
+}
+
+template <int LPR, int NV>
+void launch_pflush(const Geom &g, hipStream_t s, int cnt, const double *alphas,
+                   const double *betas, Ring<double> ring, const double *dinv, double *P,
+                   double *X) {
+    hipLaunchKernelGGL((k_pflush<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
+                       betas, ring, dinv, P, X);
 }
 
 template <int LPR, int NV, class TP>
@@ -843,6 +993,13 @@ __global__ void k_to_f32(const double *a, int64_t n, float *b) {
     if (i < n) b[i] = (float)a[i];
 }
 
+// Values of A D^-1: vs[k] = va[k] dinv[ci[k]].
+__global__ void k_scale_cols(const double *va, const int32_t *ci, const double *dinv, int64_t nnz,
+                             double *vs) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) vs[k] = va[k] * dinv[ci[k]];
+}
+
 // Preconditioner in solver row order: dinv[r] = 1 / d[perm[r]].
 __global__ void k_dinv(const double *d, const int32_t *perm, int32_t n, double *dinv) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -860,6 +1017,9 @@ struct zi_solver_ws {
     double *P[LAZY] = {};                                     // search-direction ring
     double *aring = nullptr;                                  // LAZY x ldp step lengths
     double *aflush = nullptr;                                 // LAZY x ldp scratch
+    double *bring = nullptr;                                  // LAZY x ldp betas (single-reduction)
+    double *bflush = nullptr;                                 // LAZY x ldp scratch
+    double *vs = nullptr;                                     // values of A D^-1
     double *part[3] = {nullptr, nullptr, nullptr};
     double *sc_d = nullptr;     // rho alpha beta bb rr tt (6 ldp)
     int32_t *sc_i = nullptr;    // iters active (2 ldp) + flag
@@ -898,6 +1058,9 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
     if ((st = ws->pool.alloc(&ws->X, blk)) != ZI_OK || (st = ws->pool.alloc(&ws->R, blk)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->aring, (size_t)LAZY * ldp)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->aflush, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->bring, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->bflush, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->vs, (size_t)std::max<int64_t>(sys->sp_nnz, 1))) != ZI_OK ||
         (st = ws->pool.alloc(&ws->Q, blk)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->dinv, (size_t)sys->n)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->sc_d, (size_t)6 * ldp)) != ZI_OK ||
@@ -954,6 +1117,7 @@ struct SolveCtx {
     double tol = 0, tol2 = 0;
     double eta2 = 0;          // inner-cycle reduction (squared); 0 = run to tol
     bool mixed = false, timing = false;
+    bool sr = false;          // single-reduction form (FP64)
     Scal sc{};
     EventTimer timer{nullptr};
     // event pairs per timed kernel: spmm_pq, update, pupdate, xflush
@@ -971,6 +1135,11 @@ struct SolveCtx {
     template <class TP>
     TP *P(int k) const { return reinterpret_cast<TP *>(ws->P[k % LAZY]); }
     double *alpha(int k) const { return ws->aring + (size_t)(k % LAZY) * ldp; }
+    // Single-reduction form: residual r_k in a ring of LAZY blocks (R, P[1..7];
+    // slot 0 is R, where the initial residual is formed), the lazy search
+    // direction in P[0], S = A p in Q, and the betas beside the step lengths.
+    double *Rsr(int k) const { return k % LAZY == 0 ? ws->R : ws->P[k % LAZY]; }
+    double *beta_slot(int k) const { return ws->bring + (size_t)(k % LAZY) * ldp; }
 };
 
 zi_status read_active(SolveCtx &c, hipStream_t s) {
@@ -1068,12 +1237,13 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
         Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
         ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)al, (const double *)ws->dinv,
-                       reinterpret_cast<TP *>(ws->R), (const TP *)Q, ws->part[1], ws->part[2]);
+                       (const TP *)ws->R, (const TP *)Q, reinterpret_cast<TP *>(ws->R),
+                       ws->part[1], ws->part[2]);
     }
     if ((k + 1) % LAZY == 0 || replace_r) ZI_TRY(enqueue_flush<TP>(c, k + 1, s));
     if (replace_r) ZI_TRY(true_residual(c, s, true));
     hipLaunchKernelGGL(k_red_beta, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[1], ws->part[2],
-                       g.nrt);
+                       g.nrt, (double *)nullptr);
     {
         Timed t(c, 2, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
@@ -1084,12 +1254,77 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
     return ZI_OK;
 }
 
+// Single-reduction form: X += alpha_j P_j with P_j = D^-1 R_j + beta_j P_{j-1}
+// for the pending iterations flushed .. it_end-1, one pass over P and X.
+zi_status enqueue_flush_sr(SolveCtx &c, int it_end, hipStream_t s) {
+    const int cnt = it_end - c.flushed;
+    if (cnt <= 0) return ZI_OK;
+    Ring<double> ring;
+    for (int j = 0; j < LAZY; ++j) ring.p[j] = c.Rsr(c.flushed + j);
+    const double *al = c.ws->aring, *bt = c.ws->bring;
+    if (c.flushed % LAZY != 0) {   // rotate the coefficients into contiguous blocks
+        for (int j = 0; j < cnt; ++j) {
+            ZI_HIP(hipMemcpyAsync(c.ws->aflush + (size_t)j * c.ldp, c.alpha(c.flushed + j),
+                                  sizeof(double) * c.ldp, hipMemcpyDeviceToDevice, s));
+            ZI_HIP(hipMemcpyAsync(c.ws->bflush + (size_t)j * c.ldp, c.beta_slot(c.flushed + j),
+                                  sizeof(double) * c.ldp, hipMemcpyDeviceToDevice, s));
+        }
+        al = c.ws->aflush;
+        bt = c.ws->bflush;
+    }
+    {
+        Timed t(c, 2, s, cnt == LAZY && (it_end / LAZY) % (TIMING_STRIDE / LAZY) == 0);
+        ZI_TRY(t.st);
+        ZI_TILE_SWITCH(c.tile, launch_pflush, c.g, s, cnt, al, bt, ring,
+                       (const double *)c.ws->dinv, c.ws->P[0], c.ws->X);
+    }
+    ZI_HIP(hipGetLastError());
+    c.flushed = it_end;
+    return ZI_OK;
+}
+
+// Iteration k of the single-reduction form (Chronopoulos and Gear's PCG: one
+// reduction point per iteration, the same iterates as the classic form in
+// exact arithmetic).  With r_k, gamma_k = r_k.D^-1 r_k and beta_k known:
+//   S = A D^-1 r_k + beta_k S and delta_k;  alpha_k;  [lazy P, X flush];
+//   r_{k+1} = r_k - alpha_k S with gamma_{k+1}, ||r_{k+1}||^2;  beta_{k+1}.
+// The flush of a window runs before the update that overwrites the ring slot
+// of the window's first residual.
+zi_status enqueue_iteration_sr(SolveCtx &c, int k, hipStream_t s) {
+    zi_solver_ws *ws = c.ws;
+    const Geom &g = c.g;
+    const int tile = c.tile;
+    double *al = c.alpha(k);
+    {
+        Timed t(c, 0, s, k % TIMING_STRIDE == 0);
+        ZI_TRY(t.st);
+        ZI_TILE_SWITCH(tile, launch_spmm_sr, g, s, c.sys->sp_ptr, c.sys->sp_col,
+                       (const double *)ws->vs, (const double *)ws->dinv,
+                       (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q, ws->part[0]);
+    }
+    hipLaunchKernelGGL(k_red_alpha_sr, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt);
+    if ((k + 1) % LAZY == 0) ZI_TRY(enqueue_flush_sr(c, k + 1, s));
+    {
+        Timed t(c, 1, s, k % TIMING_STRIDE == 0);
+        ZI_TRY(t.st);
+        ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)al, (const double *)ws->dinv,
+                       (const double *)c.Rsr(k), (const double *)ws->Q, c.Rsr(k + 1),
+                       ws->part[1], ws->part[2]);
+    }
+    hipLaunchKernelGGL(k_red_beta, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[1], ws->part[2],
+                       g.nrt, c.beta_slot(k + 1));
+    ZI_HIP(hipGetLastError());
+    return ZI_OK;
+}
+
 // Iterations it .. it+count-1.  In the mixed-precision mode iteration k is a
 // reliable update when (k + 1) % MIXED_REPLACE == 0.
 zi_status enqueue_iterations(SolveCtx &c, int count, hipStream_t s) {
     const int it0 = c.it;
     for (int j = 0; j < count; ++j) {
-        if (c.mixed) {
+        if (c.sr) {
+            ZI_TRY(enqueue_iteration_sr(c, it0 + j, s));
+        } else if (c.mixed) {
             ZI_TRY(enqueue_iteration<float>(c, it0 + j, c.sys->sp_val, s,
                                             (it0 + j + 1) % MIXED_REPLACE == 0));
         } else {
@@ -1100,6 +1335,7 @@ zi_status enqueue_iterations(SolveCtx &c, int count, hipStream_t s) {
 }
 
 zi_status flush_all(SolveCtx &c, hipStream_t s) {
+    if (c.sr) return enqueue_flush_sr(c, c.it, s);
     if (c.mixed) return enqueue_flush<float>(c, c.it, s);
     return enqueue_flush<double>(c, c.it, s);
 }
@@ -1184,7 +1420,16 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
         set_error("tile %d out of range", tile);
         return ZI_EINVAL;
     }
+    if (o->form != ZI_PCG_AUTO && o->form != ZI_PCG_CLASSIC && o->form != ZI_PCG_SINGLE) {
+        set_error("unknown PCG form %d", o->form);
+        return ZI_EINVAL;
+    }
     c.mixed = o->precision == ZI_FP32_SPMM_IR;
+    if (c.mixed && o->form == ZI_PCG_SINGLE) {
+        set_error("the single-reduction PCG form is FP64 only");
+        return ZI_EINVAL;
+    }
+    c.sr = !c.mixed && o->form != ZI_PCG_CLASSIC;
     ZI_TRY(ensure_ws(sys, ldp, max_nrt(n, ldp)));
     zi_solver_ws *ws = sys->ws;
     c.sys = sys;
@@ -1239,7 +1484,19 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     }
     hipLaunchKernelGGL(k_red_init, dim3(ldp), dim3(RED), 0, s, sc, ws->part[0], ws->part[1],
                        ws->part[2], c.g.nrt, L, c.tol2, c.eta2);
-    ZI_TRY(enqueue_restart_direction(c, s));
+    if (c.sr) {
+        // A D^-1, and zero S, lazy P and beta_0 (beta_0 = 0 multiplies them)
+        const int64_t nnz = sys->sp_nnz;
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s,
+                               (const double *)sys->sp_val, (const int32_t *)sys->sp_col,
+                               (const double *)ws->dinv, nnz, ws->vs);
+        ZI_TRY(fill_f64(ws->Q, 0.0, (size_t)n * ldp, s));
+        ZI_TRY(fill_f64(ws->P[0], 0.0, (size_t)n * ldp, s));
+        ZI_TRY(fill_f64(ws->bring, 0.0, (size_t)LAZY * ldp, s));
+    } else {
+        ZI_TRY(enqueue_restart_direction(c, s));
+    }
     ZI_TRY(read_active(c, s));
     c.done = !c.any_active;
     return ZI_OK;
@@ -1317,14 +1574,21 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
             const int64_t pe = c.mixed ? 4 : 8;   // bytes of a P, Q or R entry
             const int64_t ne = (int64_t)n * ldp;
             const int64_t abytes = (int64_t)c.sys->sp_nnz * 12 + (int64_t)(n + 1) * 4;
-            static const char *names[4] = {"spmm_pq", "update", "pupdate", "xflush"};
-            const int64_t bytes[4] = {
+            static const char *names_classic[4] = {"spmm_pq", "update", "pupdate", "xflush"};
+            static const char *names_sr[3] = {"spmm_sr", "update", "pflush"};
+            const int64_t bytes_classic[4] = {
                 abytes + 2 * pe * ne,                      // read P, write Q
                 3 * pe * ne + (int64_t)n * 8,              // r/w R, read Q, D^-1
                 3 * pe * ne + (int64_t)n * 8,              // read R, P; write P; D^-1
                 (16 + LAZY * pe) * ne};                    // r/w X, read LAZY directions
-            st->n_kernels = 4;
-            for (int q = 0; q < 4; ++q) {
+            const int64_t bytes_sr[3] = {
+                abytes + 24 * ne + (int64_t)n * 8,         // read R; r/w S; D^-1
+                24 * ne + (int64_t)n * 8,                  // read R, S; write R; D^-1
+                (32 + LAZY * 8) * ne + (int64_t)n * 8};    // r/w P, X; read LAZY residuals
+            const char *const *names = c.sr ? names_sr : names_classic;
+            const int64_t *bytes = c.sr ? bytes_sr : bytes_classic;
+            st->n_kernels = c.sr ? 3 : 4;
+            for (int q = 0; q < st->n_kernels; ++q) {
                 double ms = 0;
                 for (size_t k = 0; k + 1 < c.ev[q].size(); k += 2) {
                     float a = 0;
@@ -1559,6 +1823,11 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     else
         ZI_HIP(hipMemcpyAsync(ws->P[0], ws->R, sizeof(double) * n * ldp, hipMemcpyDeviceToDevice,
                               s));
+    if (precision == ZI_FP64) {   // operands of the single-reduction SpMM
+        ZI_TRY(fill_f64(ws->dinv, 1.0, (size_t)n, s));
+        ZI_TRY(fill_f64(ws->bring, 0.5, (size_t)ldp, s));
+        ZI_TRY(fill_f64(ws->Q, 0.0, (size_t)n * ldp, s));
+    }
     ZI_HIP(hipGetLastError());
     hipEvent_t e0, e1;
     ZI_HIP(hipEventCreate(&e0));
@@ -1574,9 +1843,10 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                 ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
                                (const double *)sys->sp_val, (const float *)ws->P[0],
                                reinterpret_cast<float *>(ws->Q), ws->part[0]);
-            } else {
-                ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
-                               (const double *)sys->sp_val, (const double *)ws->P[0], ws->Q,
+            } else {   // the FP64 solve's default (single-reduction) SpMM
+                ZI_TILE_SWITCH(t, launch_spmm_sr, g, s, sys->sp_ptr, sys->sp_col,
+                               (const double *)sys->sp_val, (const double *)ws->dinv,
+                               (const double *)ws->P[0], (const double *)ws->bring, ws->Q,
                                ws->part[0]);
             }
             ZI_HIP(hipEventRecord(e1, s));

@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "ZI_OK", -1: "ZI_EINVAL", -2: "ZI_EMESH", -3: "ZI_ENOMEM", -4
                 -5: "ZI_ENOTCONV", -6: "ZI_EBREAKDOWN"}
 PRECOND = {"jacobi": 0, "ldp": 1}
 PRECISION = {"fp64": 0, "fp32_spmm_ir": 1}
+PCG_FORM = {"auto": 0, "classic": 1, "single": 2}   # zi_solve_opts.form
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
 c_f64p = ctypes.POINTER(ctypes.c_double)
@@ -42,7 +43,7 @@ class ZiSolveOpts(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("graph", ctypes.c_int32), ("x0", ctypes.c_void_p),
-                ("columns", c_i32p), ("n_columns", ctypes.c_int32)]
+                ("columns", c_i32p), ("n_columns", ctypes.c_int32), ("form", ctypes.c_int32)]
 
 
 class ZiSolveStats(ctypes.Structure):
@@ -243,7 +244,7 @@ class System:
     # -- solve ---------------------------------------------------------------
     def transfer_solve(self, tol=1e-8, maxit=0, precond="jacobi", precision="fp64",
                        check_every=0, timing=False, tile=-1, x0=None, out=None,
-                       raise_on_error=True, graph=False, columns=None):
+                       raise_on_error=True, graph=False, columns=None, form="auto"):
         import torch
         cols = None if columns is None else np.ascontiguousarray(np.asarray(columns,
                                                                             dtype=np.int32))
@@ -261,7 +262,7 @@ class System:
                         int(check_every), int(bool(timing)), int(tile), int(bool(graph)),
                         _dev(x0, torch.float64, "x0") if x0 is not None else None,
                         cols.ctypes.data_as(c_i32p) if cols is not None else None,
-                        nc if cols is not None else 0)
+                        nc if cols is not None else 0, PCG_FORM[form])
         rc = lib().zi_transfer_solve(self._h, ctypes.byref(o), _dev(T, torch.float64, "T"),
                                      ctypes.byref(st), _stream())
         stats = dict(iters=iters, relres_rec=rec, relres_true=true, seconds=st.seconds,
@@ -355,7 +356,7 @@ def tile_names():
 
 
 def transfer_solve_batch(systems, tol=1e-8, maxit=0, precond="jacobi", precision="fp64",
-                         check_every=0, tile=-1, raise_on_error=True):
+                         check_every=0, tile=-1, raise_on_error=True, form="auto"):
     """zi_transfer_solve_batch over a list of System objects (one hipGraph)."""
     import torch
     k = len(systems)
@@ -373,7 +374,7 @@ def transfer_solve_batch(systems, tol=1e-8, maxit=0, precond="jacobi", precision
         sts[j].relres_rec = rec.ctypes.data_as(c_f64p)
         sts[j].relres_true = tr.ctypes.data_as(c_f64p)
     o = ZiSolveOpts(float(tol), int(maxit), PRECOND[precond], PRECISION[precision],
-                    int(check_every), 0, int(tile), 1, None, None, 0)
+                    int(check_every), 0, int(tile), 1, None, None, 0, PCG_FORM[form])
     rc = lib().zi_transfer_solve_batch(hs, k, ctypes.byref(o), tp, sts, _stream())
     if raise_on_error:
         _check(rc, "zi_transfer_solve_batch")

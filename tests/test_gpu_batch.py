@@ -28,6 +28,10 @@ def test_graph_replay_matches_eager():
     T2, s2 = g.transfer_solve(tol=1e-8, graph=True, check_every=16)
     assert torch.equal(T1, T2)
     np.testing.assert_array_equal(s1["iters"], s2["iters"])
+    T5, s5 = g.transfer_solve(tol=1e-8, form="classic")
+    T6, s6 = g.transfer_solve(tol=1e-8, graph=True, check_every=16, form="classic")
+    assert torch.equal(T5, T6)
+    np.testing.assert_array_equal(s5["iters"], s6["iters"])
     T3, s3 = g.transfer_solve(tol=1e-8, graph=True, precision="fp32_spmm_ir")
     T4, s4 = g.transfer_solve(tol=1e-8, precision="fp32_spmm_ir")
     assert torch.equal(T3, T4)

@@ -150,3 +150,20 @@ def test_single_electrode_leadfield_is_zero():
     LF = g.leadfield(T, g.point_dipoles(torch.from_numpy(H.dipole_tets).cuda()))
     assert torch.all(LF == 0)
     g.close()
+
+
+def test_pcg_form_options(head):
+    from paper_1811_07717_amd import zi
+    g = build(head)
+    _, st = g.transfer_solve(tol=1e-8, precision="fp32_spmm_ir", form="single",
+                             raise_on_error=False)
+    assert st["status"] == zi.ZI_EINVAL
+    zi.PCG_FORM["bogus"] = 7
+    try:
+        _, st = g.transfer_solve(tol=1e-8, form="bogus", raise_on_error=False)
+        assert st["status"] == zi.ZI_EINVAL
+    finally:
+        del zi.PCG_FORM["bogus"]
+    _, st = g.transfer_solve(tol=1e-8, precision="fp32_spmm_ir", form="classic")
+    assert st["status"] == zi.ZI_OK
+    g.close()

@@ -151,6 +151,26 @@ def test_deterministic(case):
     np.testing.assert_array_equal(s1["iters"], s2["iters"])
 
 
+def test_single_reduction_matches_classic(case):
+    # The single-reduction form (the FP64 default) and the classic form produce
+    # the same iterates in exact arithmetic: equal iteration counts up to a
+    # column that sits at the stopping threshold, and equal T up to rounding.
+    g = case["sys"]
+    say(f"[gpu] classic vs single-reduction PCG {case['name']}")
+    T1, s1 = g.transfer_solve(tol=1e-8, form="classic", timing=True)
+    T2, s2 = g.transfer_solve(tol=1e-8, form="single", timing=True)
+    assert set(s1["kernels"]) == {"spmm_pq", "update", "pupdate", "xflush"}
+    assert set(s2["kernels"]) == {"spmm_sr", "update", "pflush"}
+    di = np.abs(s1["iters"] - s2["iters"])
+    d = ((T1 - T2).norm(dim=0) / T1.norm(dim=0)).cpu().numpy()
+    say(f"[{case['name']}] iteration difference max {di.max()}, T difference max {d.max():.2e}")
+    assert di.max() <= 1
+    assert d[di == 0].max() <= 1e-9 and d.max() <= 1e-6
+    T3, s3 = g.transfer_solve(tol=1e-8)
+    assert torch.equal(T3, T2)
+    np.testing.assert_array_equal(s3["iters"], s2["iters"])
+
+
 def test_not_converged_returns_last_iterate(case):
     from paper_1811_07717_amd import zi
     g = case["sys"]
