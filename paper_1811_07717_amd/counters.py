@@ -29,9 +29,11 @@ KERNEL_SOURCES = ["paper_1811_07717_amd/csrc/k_pcg.hip",
 
 # rocprofv3 kernel name -> solver kernel key used by bench.py
 KERNELS = [(re.compile(r"k_spmm<.*, true>"), "spmm_pq"),
+           (re.compile(r"k_spmm_sr<"), "spmm_sr"),
            (re.compile(r"k_update<"), "update"),
            (re.compile(r"k_pupdate<"), "pupdate"),
            (re.compile(r"k_xflush<"), "xflush"),
+           (re.compile(r"k_pflush<"), "pflush"),
            (re.compile(r"k_copy2"), "copy")]
 
 
