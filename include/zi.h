@@ -309,7 +309,15 @@ typedef struct {
 zi_status zi_get_info(const zi_system *sys, zi_system_info *info);
 zi_status zi_get_view(const zi_system *sys, zi_system_view *view);
 
+/* Destroys a system.  Its device arrays and solver workspace go back to a
+ * process-wide cache of the library (the devices are synchronised first, as
+ * hipFree would), from which later zi_assemble and zi_transfer_solve calls
+ * take blocks of the same rounded size; what would take the cache beyond a
+ * quarter of the device's memory is freed at once. */
 void zi_system_destroy(zi_system *sys);
+
+/* Frees every device block held by the library's cache.  Returns ZI_OK. */
+zi_status zi_release_cached_memory(void);
 const char *zi_status_string(zi_status s);
 const char *zi_last_error(void);
 

@@ -756,6 +756,7 @@ zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t
     ZI_TRY(flags_status(hflags));
 
     zi_system *sys = new zi_system();
+    sys->pool.cached = true;
     sys->n = n;
     sys->e = e;
     sys->L = L;

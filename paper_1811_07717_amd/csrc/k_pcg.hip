@@ -1047,6 +1047,7 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
         sys->ws = nullptr;
     }
     ws = new zi_solver_ws();
+    ws->pool.cached = true;
     const size_t blk = (size_t)sys->n * ldp;
     zi_status st = ZI_OK;
     for (int j = 0; j < LAZY; ++j) {

@@ -1,4 +1,8 @@
-// Device utilities: exclusive scan, bucketing (counting sort), fills.
+// Device utilities: exclusive scan, bucketing (counting sort), fills, the
+// device block cache.
+#include <map>
+#include <mutex>
+
 #include "zi_internal.h"
 
 namespace zi {
@@ -137,6 +141,49 @@ zi_status scan_rec(const int32_t *in, int32_t *out, int32_t count, int32_t *tota
 }
 
 }  // namespace
+
+namespace {
+std::mutex g_cache_mu;
+std::multimap<std::pair<int, size_t>, void *> g_cache;   // (device, bytes) -> block
+size_t g_cached = 0;
+size_t g_cache_cap = 0;   // set on first use: a quarter of the device's memory
+}  // namespace
+
+size_t cache_round(size_t bytes) {
+    const size_t g = bytes >= (size_t(1) << 20) ? (size_t(2) << 20) : 512;
+    return (bytes + g - 1) / g * g;
+}
+
+void *cache_take(size_t bytes, int dev) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find({dev, bytes});
+    if (it == g_cache.end()) return nullptr;
+    void *p = it->second;
+    g_cache.erase(it);
+    g_cached -= bytes;
+    return p;
+}
+
+bool cache_put(void *p, size_t bytes, int dev) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (g_cache_cap == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+        g_cache_cap = tot / 4;
+    }
+    if (g_cached + bytes > g_cache_cap) return false;
+    g_cache.emplace(std::make_pair(dev, bytes), p);
+    g_cached += bytes;
+    return true;
+}
+
+zi_status cache_clear() {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto &kv : g_cache) (void)hipFree(kv.second);
+    g_cache.clear();
+    g_cached = 0;
+    return ZI_OK;
+}
 
 zi_status scan_exclusive(const int32_t *in, int32_t *out, int32_t count, Pool &pool,
                          hipStream_t s) {

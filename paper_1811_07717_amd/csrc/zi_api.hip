@@ -307,6 +307,8 @@ zi_status zi_get_view(const zi_system *sys, zi_system_view *v) {
     return ZI_OK;
 }
 
+zi_status zi_release_cached_memory(void) { return zi::cache_clear(); }
+
 void zi_system_destroy(zi_system *sys) {
     if (!sys) return;
     if (sys->ws) zi_solver_ws_destroy(sys->ws);

@@ -46,28 +46,69 @@ enum : int {
 
 constexpr int MAX_NEIGHBOURS = 128;   // distinct CSR columns per row (incl. diagonal)
 
+// Process-wide cache of device blocks (k_util.hip).  Long-lived pools (a
+// system's arrays and its solver workspace) return their blocks here when they
+// are released instead of freeing them, and take blocks of the same rounded
+// size from here first, so that building one system after another does not
+// pay for hipMalloc / hipFree (which unmaps and synchronises) every time.
+size_t cache_round(size_t bytes);
+void *cache_take(size_t bytes, int dev);
+bool cache_put(void *p, size_t bytes, int dev);   // false: over the cap, caller frees
+zi_status cache_clear();
+
 // Owned device allocation list: everything allocated through a Pool is freed
-// by release().
+// by release() (or, for a cached pool, returned to the cache).  A cached pool
+// synchronises its devices before handing its blocks back, as hipFree would.
 struct Pool {
-    std::vector<void *> ptrs;
+    struct Blk {
+        void *p;
+        size_t bytes;
+        int dev;
+    };
+    std::vector<Blk> blks;
+    bool cached = false;
     template <class T>
     zi_status alloc(T **p, size_t count) {
         *p = nullptr;
         if (count == 0) count = 1;
+        size_t bytes = count * sizeof(T);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
         void *q = nullptr;
-        hipError_t e = hipMalloc(&q, count * sizeof(T));
-        if (e != hipSuccess) {
-            set_error("hipMalloc of %zu bytes failed: %s", count * sizeof(T),
-                      hipGetErrorString(e));
-            return e == hipErrorOutOfMemory ? ZI_ENOMEM : ZI_EDEVICE;
+        if (cached) {
+            bytes = cache_round(bytes);
+            q = cache_take(bytes, dev);
         }
-        ptrs.push_back(q);
+        if (!q) {
+            hipError_t e = hipMalloc(&q, bytes);
+            if (e != hipSuccess) {
+                set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+                return e == hipErrorOutOfMemory ? ZI_ENOMEM : ZI_EDEVICE;
+            }
+        }
+        blks.push_back({q, bytes, dev});
         *p = static_cast<T *>(q);
         return ZI_OK;
     }
     void release() {
-        for (void *q : ptrs) (void)hipFree(q);
-        ptrs.clear();
+        if (cached && !blks.empty()) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            std::vector<int> devs;
+            for (const Blk &b : blks) {
+                bool seen = false;
+                for (int d : devs) seen = seen || d == b.dev;
+                if (!seen) devs.push_back(b.dev);
+            }
+            for (int d : devs) {
+                (void)hipSetDevice(d);
+                (void)hipDeviceSynchronize();
+            }
+            (void)hipSetDevice(cur);
+        }
+        for (const Blk &b : blks)
+            if (!(cached && cache_put(b.p, b.bytes, b.dev))) (void)hipFree(b.p);
+        blks.clear();
     }
     ~Pool() { release(); }
 };

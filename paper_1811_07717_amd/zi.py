@@ -111,6 +111,7 @@ SIGNATURES = [
     ("zi_get_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ZiInfo)]),
     ("zi_get_view", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ZiView)]),
     ("zi_system_destroy", None, [ctypes.c_void_p]),
+    ("zi_release_cached_memory", ctypes.c_int, []),
     ("zi_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("zi_last_error", ctypes.c_char_p, []),
 ]
@@ -349,6 +350,11 @@ def copy_probe(src, dst):
     _check(lib().zi_copy_probe(_dev(src, torch.float64, "src"), _dev(dst, torch.float64, "dst"),
                                int(src.numel()), ctypes.byref(ms), _stream()), "zi_copy_probe")
     return ms.value
+
+
+def release_cached_memory():
+    """Free the device blocks that destroyed systems left in the library's cache."""
+    _check(lib().zi_release_cached_memory(), "zi_release_cached_memory")
 
 
 def tile_names():
