@@ -1025,8 +1025,10 @@ struct zi_solver_ws {
     int32_t *sc_i = nullptr;    // iters active (2 ldp) + flag
     std::vector<hipEvent_t> ev;
     zi::Pool pool;
+    int32_t *h_pin = nullptr;   // pinned host copy of active (ldp) + flag
     ~zi_solver_ws() {
         for (auto e : ev) (void)hipEventDestroy(e);
+        if (h_pin) (void)hipHostFree(h_pin);
     }
 };
 
@@ -1074,6 +1076,13 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
             delete ws;
             return st;
         }
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&ws->h_pin), sizeof(int32_t) * (ldp + 1)) !=
+        hipSuccess) {
+        ws->h_pin = nullptr;
+        delete ws;
+        set_error("hipHostMalloc of %zu bytes failed", sizeof(int32_t) * (ldp + 1));
+        return ZI_ENOMEM;
     }
     ws->ldp = ldp;
     ws->nrt_cap = nrt_max;
@@ -1144,12 +1153,16 @@ struct SolveCtx {
 };
 
 zi_status read_active(SolveCtx &c, hipStream_t s) {
-    ZI_HIP(hipMemcpyAsync(c.h_active.data(), c.sc.active, sizeof(int32_t) * c.ldp,
+    // active (ldp) and flag are adjacent; one copy into pinned memory
+    ZI_HIP(hipMemcpyAsync(c.ws->h_pin, c.sc.active, sizeof(int32_t) * (c.ldp + 1),
                           hipMemcpyDeviceToHost, s));
-    ZI_HIP(hipMemcpyAsync(&c.h_flag, c.sc.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     ZI_HIP(hipStreamSynchronize(s));
+    c.h_flag = c.ws->h_pin[c.ldp];
     c.any_active = false;
-    for (int k = 0; k < c.ldp; ++k) c.any_active = c.any_active || c.h_active[k];
+    for (int k = 0; k < c.ldp; ++k) {
+        c.h_active[k] = c.ws->h_pin[k];
+        c.any_active = c.any_active || c.h_active[k];
+    }
     return ZI_OK;
 }
 
