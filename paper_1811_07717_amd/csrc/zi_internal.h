@@ -81,7 +81,13 @@ struct Pool {
         }
         if (!q) {
             hipError_t e = hipMalloc(&q, bytes);
+            if (e == hipErrorOutOfMemory) {   // idle cached blocks may be in the way
+                (void)hipGetLastError();
+                (void)cache_clear();
+                e = hipMalloc(&q, bytes);
+            }
             if (e != hipSuccess) {
+                (void)hipGetLastError();
                 set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
                 return e == hipErrorOutOfMemory ? ZI_ENOMEM : ZI_EDEVICE;
             }
