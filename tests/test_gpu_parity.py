@@ -171,6 +171,29 @@ def test_single_reduction_matches_classic(case):
     np.testing.assert_array_equal(s3["iters"], s2["iters"])
 
 
+@pytest.mark.parametrize("form,precision", [("single", "fp64"), ("classic", "fp64"),
+                                            ("auto", "fp32_spmm_ir")])
+def test_initial_iterate(case, form, precision):
+    # x0 = the oracle's direct solution already meets the tolerance: no
+    # iteration, T is x0 exactly.  x0 = 0.9 of it: the solve reaches the
+    # tolerance in fewer iterations than from zero.
+    g, S, Tref = case["sys"], case["S"], case["Tref"]
+    say(f"[gpu] initial iterates, {form} / {precision} {case['name']}")
+    x0 = torch.from_numpy(np.ascontiguousarray(Tref)).cuda()
+    T, st = g.transfer_solve(tol=1e-8, x0=x0, form=form, precision=precision)
+    assert (st["iters"] == 0).all()
+    assert torch.equal(T, x0)
+    T0, st0 = g.transfer_solve(tol=1e-8, form=form, precision=precision)
+    T1, st1 = g.transfer_solve(tol=1e-8, x0=0.9 * x0, form=form, precision=precision)
+    Tn = T1.cpu().numpy()
+    Bd = S["B"].toarray()
+    res = np.linalg.norm(Bd - S["A"] @ Tn, axis=0) / np.linalg.norm(Bd, axis=0)
+    say(f"[{case['name']}] from 0.9 x*: iterations {st1['iters'].max()} (from zero "
+        f"{st0['iters'].max()}), true residual max {res.max():.2e}")
+    assert res.max() <= 1.5e-8
+    assert (st1["iters"] <= st0["iters"]).all()
+
+
 def test_not_converged_returns_last_iterate(case):
     from paper_1811_07717_amd import zi
     g = case["sys"]
