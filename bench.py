@@ -47,7 +47,7 @@ def parse():
                    help="solve only the first K electrode columns (one GPU's share of a "
                         "build sharded by column) and skip the lead field, which needs all")
     p.add_argument("--no-autotune", dest="autotune", action="store_false",
-                   help="skip zi_autotune (default: tune the SpMM tile once before timing)")
+                   help="skip zi_autotune (default: tune the tile once before timing)")
     return p.parse_args()
 
 

@@ -181,12 +181,14 @@ zi_status zi_transfer_solve_batch(zi_system *const *systems, int32_t n_systems,
                                   const zi_solve_opts *opts, double *const *T,
                                   zi_solve_stats *stats, void *hip_stream);
 
-/* Autotuner: times the solver's SpMM for every tile on this system's n x L
- * block in the given precision and stores the fastest; later solves with
- * tile = -1 use it.  ZI_FP64 times the single-reduction SpMM (S = A D^-1 R +
- * beta S with its delta epilogue), ZI_FP32_SPMM_IR the classic one (Q = A P
- * with its p.q epilogue).  best_tile (HOST, may be NULL) receives it; ms (HOST, may be NULL,
- * zi_tile_count() entries) the measured milliseconds per tile. */
+/* Autotuner: scores every tile by one PCG iteration's kernels on this
+ * system's n x L block in the given precision and stores the best; later
+ * solves with tile = -1 use it.  ZI_FP64 times the single-reduction kernels
+ * (SpMM S = A D^-1 R + beta S, residual update, 1/8 of the lazy P and X
+ * flush), ZI_FP32_SPMM_IR the classic ones (SpMM Q = A P, residual update,
+ * direction update, 1/8 of the X flush); each kernel the best of three
+ * launches after a warm-up.  The workspace's contents are overwritten.  best_tile (HOST, may be NULL) receives it; ms (HOST, may be NULL,
+ * zi_tile_count() entries) the per-iteration milliseconds per tile. */
 zi_status zi_autotune(zi_system *sys, int32_t precision, int32_t *best_tile, double *ms,
                       void *hip_stream);
 

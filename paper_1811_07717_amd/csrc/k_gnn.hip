@@ -151,7 +151,7 @@ __global__ __launch_bounds__(GBLK) void k_loss_part(const float *Y, int ldy, con
     s2[threadIdx.x] = b;
     __syncthreads();
     for (int off = GBLK / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
+        if ((int)threadIdx.x < off) {
             s1[threadIdx.x] += s1[threadIdx.x + off];
             s2[threadIdx.x] += s2[threadIdx.x + off];
         }

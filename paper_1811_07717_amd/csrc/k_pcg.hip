@@ -120,10 +120,6 @@ struct Lane {
 __device__ __forceinline__ double2 ld2(const double *p) {
     return *reinterpret_cast<const double2 *>(p);
 }
-__device__ __forceinline__ double2 ld2(const float *p) {
-    const float2 v = *reinterpret_cast<const float2 *>(p);
-    return make_double2((double)v.x, (double)v.y);
-}
 __device__ __forceinline__ void st2(double *p, double2 v) {
     *reinterpret_cast<double2 *>(p) = v;
 }
@@ -169,10 +165,6 @@ struct Acc<float> {
 };
 __device__ __forceinline__ void ldpair(const double *p, double2 &v) {
     v = *reinterpret_cast<const double2 *>(p);
-}
-__device__ __forceinline__ void ldpair(const float *p, double2 &v) {
-    const float2 f = *reinterpret_cast<const float2 *>(p);
-    v = make_double2((double)f.x, (double)f.y);
 }
 __device__ __forceinline__ void ldpair(const float *p, float2 &v) {
     v = *reinterpret_cast<const float2 *>(p);
@@ -718,7 +710,7 @@ __device__ __forceinline__ double col_sum(const double *part, int nrt, int c) {
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int off = RED / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
     const double r = s[0];
@@ -1829,18 +1821,21 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     }
     ZI_TRY(ensure_ws(sys, ldp, max_nrt(n, ldp)));
     zi_solver_ws *ws = sys->ws;
-    // a smooth, non-zero block to multiply (the solver's R buffer)
-    ZI_TRY(fill_f64(ws->R, 1.0, (size_t)n * ldp, s));
-    if (precision == ZI_FP32_SPMM_IR)
-        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)(((size_t)n * ldp + 255) / 256)), dim3(256), 0,
-                           s, ws->R, (int64_t)n * ldp, reinterpret_cast<float *>(ws->P[0]));
-    else
-        ZI_HIP(hipMemcpyAsync(ws->P[0], ws->R, sizeof(double) * n * ldp, hipMemcpyDeviceToDevice,
-                              s));
-    if (precision == ZI_FP64) {   // operands of the single-reduction SpMM
-        ZI_TRY(fill_f64(ws->dinv, 1.0, (size_t)n, s));
-        ZI_TRY(fill_f64(ws->bring, 0.5, (size_t)ldp, s));
-        ZI_TRY(fill_f64(ws->Q, 0.0, (size_t)n * ldp, s));
+    const size_t blk = (size_t)n * ldp;
+    // smooth, finite operands: blocks of ones, step lengths and betas 0.5,
+    // D^-1 = 1 (the values only have to keep every kernel's arithmetic finite)
+    for (int j = 0; j < LAZY; ++j) ZI_TRY(fill_f64(ws->P[j], 1.0, blk, s));
+    ZI_TRY(fill_f64(ws->R, 1.0, blk, s));
+    ZI_TRY(fill_f64(ws->Q, 0.0, blk, s));   // also 0.0f as a float block
+    ZI_TRY(fill_f64(ws->X, 0.0, blk, s));
+    ZI_TRY(fill_f64(ws->dinv, 1.0, (size_t)n, s));
+    ZI_TRY(fill_f64(ws->aring, 0.5, (size_t)LAZY * ldp, s));
+    ZI_TRY(fill_f64(ws->bring, 0.5, (size_t)LAZY * ldp, s));
+    if (precision == ZI_FP32_SPMM_IR) {
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, ws->R,
+                           (int64_t)blk, reinterpret_cast<float *>(ws->P[0]));
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, ws->P[1],
+                           (int64_t)blk, reinterpret_cast<float *>(ws->R));
     }
     ZI_HIP(hipGetLastError());
     hipEvent_t e0, e1;
@@ -1848,30 +1843,72 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     ZI_HIP(hipEventCreate(&e1));
     int bt = 0;
     double bms = 1e30;
+    // Each tile is scored by one iteration's kernels: the SpMM, the residual
+    // update, the direction update (classic form) and 1/LAZY of the flush,
+    // each the best of three launches after a warm-up.
     for (int t = 0; t < NTILES; ++t) {
         const Geom g = make_geom(n, ldp, t);
-        double tmin = 1e30;
-        for (int rep = 0; rep < 4; ++rep) {
-            ZI_HIP(hipEventRecord(e0, s));
-            if (precision == ZI_FP32_SPMM_IR) {
-                ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
-                               (const double *)sys->sp_val, (const float *)ws->P[0],
-                               reinterpret_cast<float *>(ws->Q), ws->part[0]);
-            } else {   // the FP64 solve's default (single-reduction) SpMM
-                ZI_TILE_SWITCH(t, launch_spmm_sr, g, s, sys->sp_ptr, sys->sp_col,
-                               (const double *)sys->sp_val, (const double *)ws->dinv,
-                               (const double *)ws->P[0], (const double *)ws->bring, ws->Q,
-                               ws->part[0]);
+        double total = 0.0;
+        const int kinds = precision == ZI_FP32_SPMM_IR ? 4 : 3;
+        for (int kind = 0; kind < kinds; ++kind) {
+            double tmin = 1e30;
+            for (int rep = 0; rep < 4; ++rep) {
+                ZI_HIP(hipEventRecord(e0, s));
+                if (precision == ZI_FP32_SPMM_IR) {
+                    float *P0 = reinterpret_cast<float *>(ws->P[0]);
+                    float *P1 = reinterpret_cast<float *>(ws->P[1]);
+                    float *Qf = reinterpret_cast<float *>(ws->Q);
+                    float *Rf = reinterpret_cast<float *>(ws->R);
+                    Ring<float> ring;
+                    for (int j = 0; j < LAZY; ++j) ring.p[j] = reinterpret_cast<float *>(ws->P[j]);
+                    if (kind == 0) {
+                        ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
+                                       (const double *)sys->sp_val, (const float *)P0, Qf,
+                                       ws->part[0]);
+                    } else if (kind == 1) {
+                        ZI_TILE_SWITCH(t, launch_update, g, s, (const double *)ws->aring,
+                                       (const double *)ws->dinv, (const float *)Rf,
+                                       (const float *)Qf, Rf, ws->part[1], ws->part[2]);
+                    } else if (kind == 2) {
+                        ZI_TILE_SWITCH(t, launch_pupdate, g, s, (const double *)ws->bring,
+                                       (const double *)ws->dinv, (const float *)Rf,
+                                       (const float *)P0, P1);
+                    } else {
+                        ZI_TILE_SWITCH(t, launch_xflush, g, s, LAZY, (const double *)ws->aring,
+                                       ring, ws->X);
+                    }
+                } else {   // the FP64 solve's default (single-reduction) kernels
+                    Ring<double> ring;
+                    for (int j = 0; j < LAZY; ++j) ring.p[j] = ws->P[j];
+                    if (kind == 0) {
+                        ZI_TILE_SWITCH(t, launch_spmm_sr, g, s, sys->sp_ptr, sys->sp_col,
+                                       (const double *)sys->sp_val, (const double *)ws->dinv,
+                                       (const double *)ws->P[0], (const double *)ws->bring,
+                                       ws->Q, ws->part[0]);
+                    } else if (kind == 1) {
+                        ZI_TILE_SWITCH(t, launch_update, g, s, (const double *)ws->aring,
+                                       (const double *)ws->dinv, (const double *)ws->P[0],
+                                       (const double *)ws->Q, ws->P[1], ws->part[1],
+                                       ws->part[2]);
+                    } else {
+                        ZI_TILE_SWITCH(t, launch_pflush, g, s, LAZY, (const double *)ws->aring,
+                                       (const double *)ws->bring, ring,
+                                       (const double *)ws->dinv, ws->R, ws->X);
+                    }
+                }
+                ZI_HIP(hipGetLastError());
+                ZI_HIP(hipEventRecord(e1, s));
+                ZI_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                ZI_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) tmin = std::min(tmin, (double)ms);   // first run warms up
             }
-            ZI_HIP(hipEventRecord(e1, s));
-            ZI_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            ZI_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0) tmin = std::min(tmin, (double)ms);   // first run warms up
+            const bool flush = kind == kinds - 1;
+            total += flush ? tmin / LAZY : tmin;
         }
-        if (ms_out) ms_out[t] = tmin;
-        if (tmin < bms) {
-            bms = tmin;
+        if (ms_out) ms_out[t] = total;
+        if (total < bms) {
+            bms = total;
             bt = t;
         }
     }

@@ -278,7 +278,7 @@ class System:
         return T, stats
 
     def autotune(self, precision="fp64"):
-        """Time every SpMM tile on this system; later solves use the fastest."""
+        """Score every tile by one PCG iteration's kernels; later solves use the best."""
         n = lib().zi_tile_count()
         ms = np.zeros(n)
         best = ctypes.c_int32(-1)
