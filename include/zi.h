@@ -101,7 +101,7 @@ enum { ZI_PCG_AUTO = 0,       /* single-reduction in ZI_FP64, classic in
                                  r.D^-1 r); every search direction is formed */
        ZI_PCG_SINGLE = 2      /* single-reduction form of Chronopoulos and Gear:
                                  s = A D^-1 r + beta s by recurrence, the search
-                                 directions are formed lazily beside x every 8
+                                 directions are formed lazily beside x every 16
                                  iterations; ZI_FP64 only */ };
 
 /* Options of zi_transfer_solve.  Zero-initialised fields take defaults. */
@@ -111,7 +111,9 @@ typedef struct {
     int32_t maxit;       /* iteration limit per column; 0 -> 50000 */
     int32_t precond;     /* ZI_PREC_JACOBI or ZI_PREC_LDP */
     int32_t precision;   /* ZI_FP64 or ZI_FP32_SPMM_IR */
-    int32_t check_every; /* iterations between host convergence checks; 0 -> 8 */
+    int32_t check_every; /* iterations between host convergence checks; 0 -> 8;
+                            rounded up to a multiple of 8, and of 16 for
+                            graph replays of the FP64 single-reduction form */
     int32_t timing;      /* 1: time the solver kernels with HIP events
                             (the launches of every 8th iteration) */
     int32_t tile;        /* SpMM tile id (see zi_tile_count); -1 -> the tile
@@ -184,11 +186,13 @@ zi_status zi_transfer_solve_batch(zi_system *const *systems, int32_t n_systems,
 /* Autotuner: scores every tile by one PCG iteration's kernels on this
  * system's n x L block in the given precision and stores the best; later
  * solves with tile = -1 use it.  ZI_FP64 times the single-reduction kernels
- * (SpMM S = A D^-1 R + beta S, residual update, 1/8 of the lazy P and X
- * flush), ZI_FP32_SPMM_IR the classic ones (SpMM Q = A P, residual update,
- * direction update, 1/8 of the X flush); each kernel the best of three
- * launches after a warm-up.  The workspace's contents are overwritten.  best_tile (HOST, may be NULL) receives it; ms (HOST, may be NULL,
- * zi_tile_count() entries) the per-iteration milliseconds per tile. */
+ * (SpMM S = A D^-1 R + beta S and the residual update; the lazy P and X
+ * flush has a fixed geometry), ZI_FP32_SPMM_IR the classic ones (SpMM
+ * Q = A P, residual update, direction update, 1/8 of the X flush); each
+ * kernel the best of three launches after a warm-up.  The workspace's
+ * contents are overwritten.  best_tile (HOST, may be NULL) receives the
+ * choice; ms (HOST, may be NULL, zi_tile_count() entries) the per-iteration
+ * milliseconds per tile. */
 zi_status zi_autotune(zi_system *sys, int32_t precision, int32_t *best_tile, double *ms,
                       void *hip_stream);
 

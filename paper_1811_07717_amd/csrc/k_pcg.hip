@@ -477,11 +477,16 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
     block_partials<LPR, NV, 2>(g, ln, sc.cc, sc.prow, acc, parts);
 }
 
-// Ring of the last LAZY search directions and their step lengths.
+// Ring of the last LAZY search directions and their step lengths (classic
+// form), and of the last LAZY_SR residuals (single-reduction form).
 constexpr int LAZY = 8;
+constexpr int LAZY_SR = 16;
 template <class TP>
 struct Ring {
     const TP *p[LAZY];
+};
+struct RingSR {
+    const double *p[LAZY_SR];
 };
 
 // X += sum_{j < cnt} alpha_j P_j (in ring order: the iterations' order).
@@ -531,26 +536,30 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
 // Lazy search directions of the single-reduction PCG (FP64): for the
 // iterations j < cnt of the window, in order, P = D^-1 R_j + beta_j P and
 // X += alpha_j P, with the same fused multiply-adds as the direction update
-// and the X flush of the classic form; one pass over P and X per window.
+// and the X flush of the classic form; one pass over P and X per window of
+// up to LAZY_SR iterations.  The window's step lengths and betas of the
+// block's columns sit in LDS (LAZY_SR of each per column pair would not fit
+// in registers); the residuals are read eight at a time.
 template <int LPR, int NV>
 __global__ __launch_bounds__(BLOCK) void k_pflush(Geom g, int cnt, const double *__restrict__ alphas,
-                                                  const double *__restrict__ betas,
-                                                  Ring<double> ring,
+                                                  const double *__restrict__ betas, RingSR ring,
                                                   const double *__restrict__ dinv,
                                                   double *__restrict__ P,
                                                   double *__restrict__ X) {
+    constexpr int CP = Lane<LPR, NV>::CW / 2;   // column pairs of the chunk
+    constexpr int HALF = LAZY_SR / 2;
+    __shared__ double2 cf[2][LAZY_SR][CP];
     Sched sc;
-    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;   // whole block
     Lane<LPR, NV> ln(g, sc.cc);
-    double2 al[LAZY][NV], bt[LAZY][NV];
-#pragma unroll
-    for (int j = 0; j < LAZY; ++j)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const bool on = j < cnt && ln.ok[v];
-            al[j][v] = on ? ld2(alphas + (size_t)j * g.ldp + ln.c[v]) : make_double2(0.0, 0.0);
-            bt[j][v] = on ? ld2(betas + (size_t)j * g.ldp + ln.c[v]) : make_double2(0.0, 0.0);
-        }
+    for (int i = threadIdx.x; i < 2 * LAZY_SR * CP; i += BLOCK) {
+        const int q = i / (LAZY_SR * CP), j = (i / CP) % LAZY_SR, cp = i % CP;
+        const int col = sc.cc * 2 * CP + 2 * cp;
+        cf[q][j][cp] = (j < cnt && col < g.ldp)
+                           ? ld2((q ? betas : alphas) + (size_t)j * g.ldp + col)
+                           : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
     for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
         const int row = base + ln.slot;
         if (row >= sc.re) continue;
@@ -558,19 +567,27 @@ __global__ __launch_bounds__(BLOCK) void k_pflush(Geom g, int cnt, const double 
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (!ln.ok[v]) continue;
+            const int cp = ln.lr + LPR * v;
             const size_t o = (size_t)row * g.ldp + ln.c[v];
-            double2 r[LAZY];
-#pragma unroll
-            for (int j = 0; j < LAZY; ++j) r[j] = j < cnt ? ldn2(ring.p[j] + o) : make_double2(0.0, 0.0);
             double2 p = ldn2(P + o);
             double2 x = ldn2(X + o);
 #pragma unroll
-            for (int j = 0; j < LAZY; ++j) {
-                if (j < cnt) {
-                    p.x = fma(bt[j][v].x, p.x, r[j].x * di);
-                    p.y = fma(bt[j][v].y, p.y, r[j].y * di);
-                    x.x = fma(al[j][v].x, p.x, x.x);
-                    x.y = fma(al[j][v].y, p.y, x.y);
+            for (int h = 0; h < 2; ++h) {
+                double2 r[HALF];
+#pragma unroll
+                for (int j = 0; j < HALF; ++j)
+                    r[j] = h * HALF + j < cnt ? ldn2(ring.p[h * HALF + j] + o)
+                                              : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int j = 0; j < HALF; ++j) {
+                    const int jj = h * HALF + j;
+                    if (jj < cnt) {
+                        const double2 a = cf[0][jj][cp], b = cf[1][jj][cp];
+                        p.x = fma(b.x, p.x, r[j].x * di);
+                        p.y = fma(b.y, p.y, r[j].y * di);
+                        x.x = fma(a.x, p.x, x.x);
+                        x.y = fma(a.y, p.y, x.y);
+                    }
                 }
             }
             stn2(P + o, p);
@@ -842,7 +859,7 @@ struct TileCfg {
     const char *name;
 };
 
-const TileCfg kTiles[] = {
+constexpr TileCfg kTiles[] = {
     {64, 1, 0, "lpr64_nv1_cw128"},       {64, 2, 0, "lpr64_nv2_cw256"},
     {32, 1, 0, "lpr32_nv1_cw64"},        {32, 2, 0, "lpr32_nv2_cw128"},
     {16, 1, 0, "lpr16_nv1_cw32"},        {16, 2, 0, "lpr16_nv2_cw64"},
@@ -950,11 +967,18 @@ void launch_spmm_sr(const Geom &g, hipStream_t s, const int32_t *rp, const int32
                        dinv, R, beta, S, part);
 }
 
-template <int LPR, int NV>
-void launch_pflush(const Geom &g, hipStream_t s, int cnt, const double *alphas,
-                   const double *betas, Ring<double> ring, const double *dinv, double *P,
-                   double *X) {
-    hipLaunchKernelGGL((k_pflush<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
+// The flush writes no partial sums, so it runs with its own geometry: the
+// cooperative front of 32 lanes x 2 pairs per row (128-column chunks), the
+// fastest for it on the 2 mm sphere, whatever tile the SpMM uses.
+constexpr int FLUSH_TILE = 13;   // lpr32_nv2_cw128_front
+static_assert(kTiles[FLUSH_TILE].lpr == 32 && kTiles[FLUSH_TILE].nv == 2 &&
+                  kTiles[FLUSH_TILE].front == 1,
+              "flush geometry");
+
+void launch_pflush(int n, int ldp, hipStream_t s, int cnt, const double *alphas,
+                   const double *betas, RingSR ring, const double *dinv, double *P, double *X) {
+    const Geom g = make_geom(n, ldp, FLUSH_TILE);
+    hipLaunchKernelGGL((k_pflush<32, 2>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
                        betas, ring, dinv, P, X);
 }
 
@@ -1006,7 +1030,7 @@ __global__ void k_dinv(const double *d, const int32_t *perm, int32_t n, double *
 struct zi_solver_ws {
     int ldp = 0, nrt_cap = 0;
     double *X = nullptr, *R = nullptr, *Q = nullptr, *dinv = nullptr;
-    double *P[LAZY] = {};                                     // search-direction ring
+    double *P[LAZY_SR] = {};   // search-direction ring (classic: 0..7); lazy P and residual ring
     double *aring = nullptr;                                  // LAZY x ldp step lengths
     double *aflush = nullptr;                                 // LAZY x ldp scratch
     double *bring = nullptr;                                  // LAZY x ldp betas (single-reduction)
@@ -1044,17 +1068,17 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
     ws->pool.cached = true;
     const size_t blk = (size_t)sys->n * ldp;
     zi_status st = ZI_OK;
-    for (int j = 0; j < LAZY; ++j) {
+    for (int j = 0; j < LAZY_SR; ++j) {
         if ((st = ws->pool.alloc(&ws->P[j], blk)) != ZI_OK) {
             delete ws;
             return st;
         }
     }
     if ((st = ws->pool.alloc(&ws->X, blk)) != ZI_OK || (st = ws->pool.alloc(&ws->R, blk)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->aring, (size_t)LAZY * ldp)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->aflush, (size_t)LAZY * ldp)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->bring, (size_t)LAZY * ldp)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->bflush, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->aring, (size_t)LAZY_SR * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->aflush, (size_t)LAZY_SR * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->bring, (size_t)LAZY_SR * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->bflush, (size_t)LAZY_SR * ldp)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->vs, (size_t)std::max<int64_t>(sys->sp_nnz, 1))) != ZI_OK ||
         (st = ws->pool.alloc(&ws->Q, blk)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->dinv, (size_t)sys->n)) != ZI_OK ||
@@ -1136,12 +1160,13 @@ struct SolveCtx {
     std::chrono::steady_clock::time_point t_start;
     template <class TP>
     TP *P(int k) const { return reinterpret_cast<TP *>(ws->P[k % LAZY]); }
-    double *alpha(int k) const { return ws->aring + (size_t)(k % LAZY) * ldp; }
-    // Single-reduction form: residual r_k in a ring of LAZY blocks (R, P[1..7];
-    // slot 0 is R, where the initial residual is formed), the lazy search
-    // direction in P[0], S = A p in Q, and the betas beside the step lengths.
-    double *Rsr(int k) const { return k % LAZY == 0 ? ws->R : ws->P[k % LAZY]; }
-    double *beta_slot(int k) const { return ws->bring + (size_t)(k % LAZY) * ldp; }
+    int lazy() const { return sr ? LAZY_SR : LAZY; }
+    double *alpha(int k) const { return ws->aring + (size_t)(k % lazy()) * ldp; }
+    // Single-reduction form: residual r_k in a ring of LAZY_SR blocks (R,
+    // P[1..15]; slot 0 is R, where the initial residual is formed), the lazy
+    // search direction in P[0], S = A p in Q, the betas beside the step lengths.
+    double *Rsr(int k) const { return k % LAZY_SR == 0 ? ws->R : ws->P[k % LAZY_SR]; }
+    double *beta_slot(int k) const { return ws->bring + (size_t)(k % LAZY_SR) * ldp; }
 };
 
 zi_status read_active(SolveCtx &c, hipStream_t s) {
@@ -1265,10 +1290,10 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
 zi_status enqueue_flush_sr(SolveCtx &c, int it_end, hipStream_t s) {
     const int cnt = it_end - c.flushed;
     if (cnt <= 0) return ZI_OK;
-    Ring<double> ring;
-    for (int j = 0; j < LAZY; ++j) ring.p[j] = c.Rsr(c.flushed + j);
+    RingSR ring;
+    for (int j = 0; j < LAZY_SR; ++j) ring.p[j] = c.Rsr(c.flushed + j);
     const double *al = c.ws->aring, *bt = c.ws->bring;
-    if (c.flushed % LAZY != 0) {   // rotate the coefficients into contiguous blocks
+    if (c.flushed % LAZY_SR != 0) {   // rotate the coefficients into contiguous blocks
         for (int j = 0; j < cnt; ++j) {
             ZI_HIP(hipMemcpyAsync(c.ws->aflush + (size_t)j * c.ldp, c.alpha(c.flushed + j),
                                   sizeof(double) * c.ldp, hipMemcpyDeviceToDevice, s));
@@ -1279,10 +1304,10 @@ zi_status enqueue_flush_sr(SolveCtx &c, int it_end, hipStream_t s) {
         bt = c.ws->bflush;
     }
     {
-        Timed t(c, 2, s, cnt == LAZY && (it_end / LAZY) % (TIMING_STRIDE / LAZY) == 0);
+        Timed t(c, 2, s, cnt == LAZY_SR);
         ZI_TRY(t.st);
-        ZI_TILE_SWITCH(c.tile, launch_pflush, c.g, s, cnt, al, bt, ring,
-                       (const double *)c.ws->dinv, c.ws->P[0], c.ws->X);
+        launch_pflush(c.sys->n, c.ldp, s, cnt, al, bt, ring, (const double *)c.ws->dinv,
+                      c.ws->P[0], c.ws->X);
     }
     ZI_HIP(hipGetLastError());
     c.flushed = it_end;
@@ -1309,7 +1334,7 @@ zi_status enqueue_iteration_sr(SolveCtx &c, int k, hipStream_t s) {
                        (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q, ws->part[0]);
     }
     hipLaunchKernelGGL(k_red_alpha_sr, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt);
-    if ((k + 1) % LAZY == 0) ZI_TRY(enqueue_flush_sr(c, k + 1, s));
+    if ((k + 1) % LAZY_SR == 0) ZI_TRY(enqueue_flush_sr(c, k + 1, s));
     {
         Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
@@ -1389,7 +1414,10 @@ int pick_tile(const zi_system *sys, int ldp, int precision, int requested) {
 
 // Validate options, prepare the workspace and enqueue the initial state:
 // X = x0 or 0, R = B - A X, the per-column scalars and P = D^-1 R.
-zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipStream_t s) {
+// graphs: the iterations will be replayed as captured chunks (zi_solve_impl
+// with opts.graph, and every batch).
+zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipStream_t s,
+                      bool graphs) {
     c.t_start = std::chrono::steady_clock::now();
     const int n = sys->n;
     const int L = o->columns ? o->n_columns : sys->L;
@@ -1446,7 +1474,10 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     c.L = L;
     c.maxit = o->maxit > 0 ? o->maxit : 50000;
     c.check = o->check_every > 0 ? o->check_every : 8;
-    c.check = ((c.check + LAZY - 1) / LAZY) * LAZY;   // chunks end on an X flush
+    c.check = ((c.check + LAZY - 1) / LAZY) * LAZY;
+    // a replayed graph chunk must end on an X flush (the single-reduction
+    // form flushes every LAZY_SR iterations; eager solves check every LAZY)
+    if (c.sr && graphs) c.check = ((c.check + LAZY_SR - 1) / LAZY_SR) * LAZY_SR;
     if (c.mixed) {   // a divisor of MIXED_REPLACE: captured chunks repeat per phase
         int q = LAZY;
         while (q < c.check && q < MIXED_REPLACE) q *= 2;
@@ -1499,7 +1530,7 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
                                (const double *)ws->dinv, nnz, ws->vs);
         ZI_TRY(fill_f64(ws->Q, 0.0, (size_t)n * ldp, s));
         ZI_TRY(fill_f64(ws->P[0], 0.0, (size_t)n * ldp, s));
-        ZI_TRY(fill_f64(ws->bring, 0.0, (size_t)LAZY * ldp, s));
+        ZI_TRY(fill_f64(ws->bring, 0.0, (size_t)LAZY_SR * ldp, s));
     } else {
         ZI_TRY(enqueue_restart_direction(c, s));
     }
@@ -1590,7 +1621,7 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
             const int64_t bytes_sr[3] = {
                 abytes + 24 * ne + (int64_t)n * 8,         // read R; r/w S; D^-1
                 24 * ne + (int64_t)n * 8,                  // read R, S; write R; D^-1
-                (32 + LAZY * 8) * ne + (int64_t)n * 8};    // r/w P, X; read LAZY residuals
+                (32 + LAZY_SR * 8) * ne + (int64_t)n * 8};   // r/w P, X; read LAZY_SR residuals
             const char *const *names = c.sr ? names_sr : names_classic;
             const int64_t *bytes = c.sr ? bytes_sr : bytes_classic;
             st->n_kernels = c.sr ? 3 : 4;
@@ -1691,7 +1722,7 @@ zi_status capture_graph(std::vector<SolveCtx *> &cs, std::vector<hipStream_t> &s
 zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_solve_stats *st,
                         hipStream_t s) {
     SolveCtx c;
-    ZI_TRY(solve_begin(sys, o, c, s));
+    ZI_TRY(solve_begin(sys, o, c, s, o->graph != 0));
     if (o->graph) {
         std::vector<SolveCtx *> cs{&c};
         hipStream_t side, cap;
@@ -1743,7 +1774,7 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
                               double *const *T, zi_solve_stats *st, hipStream_t s) {
     std::vector<SolveCtx> cs(nsys);
     for (int k = 0; k < nsys; ++k) {
-        ZI_TRY(solve_begin(systems[k], o, cs[k], s));
+        ZI_TRY(solve_begin(systems[k], o, cs[k], s, true));
         cs[k].timing = false;   // events cannot be captured
     }
     std::vector<hipStream_t> streams(nsys + 1);   // one per system + capture origin
@@ -1849,7 +1880,7 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     for (int t = 0; t < NTILES; ++t) {
         const Geom g = make_geom(n, ldp, t);
         double total = 0.0;
-        const int kinds = precision == ZI_FP32_SPMM_IR ? 4 : 3;
+        const int kinds = precision == ZI_FP32_SPMM_IR ? 4 : 2;
         for (int kind = 0; kind < kinds; ++kind) {
             double tmin = 1e30;
             for (int rep = 0; rep < 4; ++rep) {
@@ -1878,22 +1909,16 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                                        ring, ws->X);
                     }
                 } else {   // the FP64 solve's default (single-reduction) kernels
-                    Ring<double> ring;
-                    for (int j = 0; j < LAZY; ++j) ring.p[j] = ws->P[j];
                     if (kind == 0) {
                         ZI_TILE_SWITCH(t, launch_spmm_sr, g, s, sys->sp_ptr, sys->sp_col,
                                        (const double *)sys->sp_val, (const double *)ws->dinv,
                                        (const double *)ws->P[0], (const double *)ws->bring,
                                        ws->Q, ws->part[0]);
-                    } else if (kind == 1) {
+                    } else {
                         ZI_TILE_SWITCH(t, launch_update, g, s, (const double *)ws->aring,
                                        (const double *)ws->dinv, (const double *)ws->P[0],
                                        (const double *)ws->Q, ws->P[1], ws->part[1],
                                        ws->part[2]);
-                    } else {
-                        ZI_TILE_SWITCH(t, launch_pflush, g, s, LAZY, (const double *)ws->aring,
-                                       (const double *)ws->bring, ring,
-                                       (const double *)ws->dinv, ws->R, ws->X);
                     }
                 }
                 ZI_HIP(hipGetLastError());
@@ -1903,7 +1928,9 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                 ZI_HIP(hipEventElapsedTime(&ms, e0, e1));
                 if (rep > 0) tmin = std::min(tmin, (double)ms);   // first run warms up
             }
-            const bool flush = kind == kinds - 1;
+            // the classic form's X flush runs every LAZY iterations; the
+            // single-reduction flush has its own geometry and is not scored
+            const bool flush = precision == ZI_FP32_SPMM_IR && kind == kinds - 1;
             total += flush ? tmin / LAZY : tmin;
         }
         if (ms_out) ms_out[t] = total;
