@@ -115,7 +115,8 @@ typedef struct {
                             rounded up to a multiple of 8, and of 16 for
                             graph replays of the FP64 single-reduction form */
     int32_t timing;      /* 1: time the solver kernels with HIP events
-                            (the launches of every 8th iteration) */
+                            (the SpMM and updates of every 8th
+                            iteration, and every full flush) */
     int32_t tile;        /* SpMM tile id (see zi_tile_count); -1 -> the tile
                             zi_autotune chose, else a width-based default */
     int32_t graph;       /* 1: replay the iteration loop as a hipGraph of
@@ -141,7 +142,7 @@ typedef struct {
     int32_t tile;          /* SpMM tile used */
     int32_t n_kernels;     /* entries used in the arrays below */
     double kernel_ms[8];   /* total event-timed ms per solver kernel */
-    int32_t kernel_launches[8]; /* launches timed (a sample of every 8th) */
+    int32_t kernel_launches[8]; /* launches timed (the sample above) */
     int64_t kernel_bytes[8]; /* algorithmic bytes of one launch */
     const char *kernel_name[8];
     int32_t kernel_calls[8];   /* launches in the solve (timed or not) */
