@@ -213,49 +213,74 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
 // Four waves per block, 16 output columns each (64 per block).  W is staged
-// in LDS GK columns at a time (rows padded to GK + 1 so that the 16 rows a
-// wave reads per MFMA fall in different banks); every wave forms all MT row
-// tiles of its columns from the staged chunk, so W is read once per 64 output
-// columns and the B operand once per k step.
+// in LDS gk(MT) columns at a time (rows padded to gk + 1 so that the 16 rows a
+// wave reads per MFMA fall in different banks) in two alternating buffers:
+// the next chunk of W and of the B operand (Pt) is requested before the MFMAs
+// of the current one and stored after them, so one barrier per chunk orders
+// the buffers and no MFMA waits for a global load.  Every wave forms all MT
+// row tiles of its columns from the staged chunk, so W is read once per 64
+// output columns and the B operand once per k step.
 constexpr int GEMM_THREADS = 256;
-constexpr int GK = 16;
+template <int MT>
+constexpr int gk() { return MT <= 8 ? 16 : 8; }   // two buffers stay within 64 KB
 
 template <int MT, class F>
 __device__ __forceinline__ void gemm_tile(const double *W, const double *Pt, int L, int n_cols,
-                                          double (*Ws)[GK + 1], F mfma_step) {
+                                          double (*Ws)[MT * 16][gk<MT>() + 1], F mfma_step) {
+    constexpr int GK = gk<MT>();
+    constexpr int NW = MT * 16 * GK;                              // W entries per chunk
+    constexpr int PER = (NW + GEMM_THREADS - 1) / GEMM_THREADS;   // per thread
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = blockIdx.x * 64 + wv * 16 + (t & 15);
     const int kq = t >> 4;
-    for (int k0 = 0; k0 < L; k0 += GK) {
-        __syncthreads();   // previous chunk consumed
-        for (int idx = threadIdx.x; idx < MT * 16 * GK; idx += GEMM_THREADS) {
-            const int r = idx / GK, kk = idx % GK;
-            Ws[r][kk] = (r < L && k0 + kk < L) ? W[(size_t)r * L + k0 + kk] : 0.0;
-        }
-        __syncthreads();
+    const int nchunk = (L + GK - 1) / GK;
+    double wreg[PER], breg[GK / 4];
+    auto request = [&](int k0) {
 #pragma unroll
-        for (int kk = 0; kk < GK; kk += 4) {
-            const int k = k0 + kk + kq;
-            const double b = (col < n_cols && k < L) ? Pt[(size_t)col * L + k] : 0.0;
-            mfma_step(kk + kq, b);
+        for (int i = 0; i < PER; ++i) {
+            const int idx = threadIdx.x + i * GEMM_THREADS;
+            const int r = idx / GK, kk = idx % GK;
+            wreg[i] = (idx < NW && r < L && k0 + kk < L) ? W[(size_t)r * L + k0 + kk] : 0.0;
         }
+#pragma unroll
+        for (int j = 0; j < GK / 4; ++j) {
+            const int k = k0 + 4 * j + kq;
+            breg[j] = (col < n_cols && k < L) ? Pt[(size_t)col * L + k] : 0.0;
+        }
+    };
+    request(0);
+    for (int c = 0; c < nchunk; ++c) {
+        const int buf = c & 1;
+        // buffer buf was last read in chunk c - 2, before the previous barrier
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = threadIdx.x + i * GEMM_THREADS;
+            if (idx < NW) Ws[buf][idx / GK][idx % GK] = wreg[i];
+        }
+        double bcur[GK / 4];
+#pragma unroll
+        for (int j = 0; j < GK / 4; ++j) bcur[j] = breg[j];
+        __syncthreads();
+        if (c + 1 < nchunk) request((c + 1) * GK);
+#pragma unroll
+        for (int j = 0; j < GK / 4; ++j) mfma_step(Ws[buf], 4 * j + kq, bcur[j]);
     }
 }
 
 template <int MT>
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f64(const double *W, const double *Pt,
                                                            int L, int n_cols, double *LF) {
-    __shared__ double Ws[MT * 16][GK + 1];
+    __shared__ double Ws[2][MT * 16][gk<MT>() + 1];
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = blockIdx.x * 64 + wv * 16 + (t & 15);
     const int kq = t >> 4;
     dbl4 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = dbl4{0.0, 0.0, 0.0, 0.0};
-    gemm_tile<MT>(W, Pt, L, n_cols, Ws, [&](int kk, double b) {
+    gemm_tile<MT>(W, Pt, L, n_cols, Ws, [&](const double (*Wb)[gk<MT>() + 1], int kk, double b) {
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ws[m * 16 + (t & 15)][kk], b, acc[m],
+            acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(Wb[m * 16 + (t & 15)][kk], b, acc[m],
                                                           0, 0, 0);
     });
     if (col >= n_cols) return;
@@ -271,17 +296,17 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f64(const double *W, cons
 template <int MT>
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f32(const double *W, const double *Pt,
                                                            int L, int n_cols, double *LF) {
-    __shared__ double Ws[MT * 16][GK + 1];
+    __shared__ double Ws[2][MT * 16][gk<MT>() + 1];
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = blockIdx.x * 64 + wv * 16 + (t & 15);
     const int kq = t >> 4;
     flt4 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = flt4{0.f, 0.f, 0.f, 0.f};
-    gemm_tile<MT>(W, Pt, L, n_cols, Ws, [&](int kk, double b) {
+    gemm_tile<MT>(W, Pt, L, n_cols, Ws, [&](const double (*Wb)[gk<MT>() + 1], int kk, double b) {
 #pragma unroll
         for (int m = 0; m < MT; ++m)
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)Ws[m * 16 + (t & 15)][kk],
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)Wb[m * 16 + (t & 15)][kk],
                                                           (float)b, acc[m], 0, 0, 0);
     });
     if (col >= n_cols) return;
