@@ -98,7 +98,8 @@ enum { ZI_FP64 = 0,         /* all arithmetic in float64 */
 enum { ZI_PCG_AUTO = 0,       /* single-reduction in ZI_FP64, classic in
                                  ZI_FP32_SPMM_IR */
        ZI_PCG_CLASSIC = 1,    /* two reductions per iteration (p.Ap, then
-                                 r.D^-1 r); every search direction is formed */
+                                 r.D^-1 r); every search direction is formed,
+                                 x is updated every 16 iterations */
        ZI_PCG_SINGLE = 2      /* single-reduction form of Chronopoulos and Gear:
                                  s = A D^-1 r + beta s by recurrence, the search
                                  directions are formed lazily beside x every 16
@@ -112,8 +113,10 @@ typedef struct {
     int32_t precond;     /* ZI_PREC_JACOBI or ZI_PREC_LDP */
     int32_t precision;   /* ZI_FP64 or ZI_FP32_SPMM_IR */
     int32_t check_every; /* iterations between host convergence checks; 0 -> 8;
-                            rounded up to a multiple of 8, and of 16 for
-                            graph replays of the FP64 single-reduction form */
+                            rounded up to a multiple of 8, and of 16 when the
+                            iterations are replayed as graphs (graph = 1 and
+                            every batch); in ZI_FP32_SPMM_IR further up to a
+                            power of two that divides 64 */
     int32_t timing;      /* 1: time the solver kernels with HIP events
                             (the SpMM and updates of every 8th
                             iteration, and every full flush) */

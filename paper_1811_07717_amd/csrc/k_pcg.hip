@@ -477,35 +477,41 @@ __global__ __launch_bounds__(BLOCK) void k_update(Geom g, const double *__restri
     block_partials<LPR, NV, 2>(g, ln, sc.cc, sc.prow, acc, parts);
 }
 
-// Ring of the last LAZY search directions and their step lengths (classic
-// form), and of the last LAZY_SR residuals (single-reduction form).
-constexpr int LAZY = 8;
-constexpr int LAZY_SR = 16;
+// X is updated every LAZY iterations from a ring of the last LAZY search
+// directions (classic form) or residuals (single-reduction form); the host
+// checks convergence every CHECK_MIN iterations or more.
+constexpr int LAZY = 16;
+constexpr int CHECK_MIN = 8;
 template <class TP>
 struct Ring {
     const TP *p[LAZY];
 };
-struct RingSR {
-    const double *p[LAZY_SR];
-};
 
-// X += sum_{j < cnt} alpha_j P_j (in ring order: the iterations' order).
-template <int LPR, int NV, class TP>
+// X += sum_{j < cnt} alpha_j P_j (in ring order: the iterations' order), one
+// pass over X per window of up to LAZY iterations.  Fixed geometry (32 lanes
+// x 2 pairs per row, 128-column chunks, as the single-reduction flush); the
+// window's step lengths of the block's columns sit in LDS and the directions
+// are read eight at a time.  FP32 rings: unconditional loads from clamped
+// addresses (slots past cnt read slot 0, cnt >= 1), masked at the store, as
+// in k_update.
+template <class TP>
 __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double *__restrict__ alphas,
                                                   Ring<TP> ring, double *__restrict__ X) {
-    Sched sc;
-    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
-    Lane<LPR, NV> ln(g, sc.cc);
-    double2 al[LAZY][NV];
-#pragma unroll
-    for (int j = 0; j < LAZY; ++j)
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-            al[j][v] = (j < cnt && ln.ok[v]) ? ld2(alphas + (size_t)j * g.ldp + ln.c[v])
-                                             : make_double2(0.0, 0.0);
-    // FP32 rings: unconditional loads from clamped addresses (slots past cnt
-    // read slot 0, cnt >= 1), masked at the store, as in k_update.
+    constexpr int LPR = 32, NV = 2;
+    constexpr int CP = Lane<LPR, NV>::CW / 2;
+    constexpr int HALF = LAZY / 2;
     constexpr bool CL = clamp_loads<TP>();
+    __shared__ double2 cf[LAZY][CP];
+    Sched sc;
+    if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;   // whole block
+    Lane<LPR, NV> ln(g, sc.cc);
+    for (int i = threadIdx.x; i < LAZY * CP; i += BLOCK) {
+        const int j = i / CP, cp = i % CP;
+        const int col = sc.cc * 2 * CP + 2 * cp;
+        cf[j][cp] = (j < cnt && col < g.ldp) ? ld2(alphas + (size_t)j * g.ldp + col)
+                                             : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
     __builtin_assume(cnt >= 1);   // the host launches no empty flush
     for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
         const int row = base + ln.slot;
@@ -514,18 +520,26 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (!CL && !ln.ok[v]) continue;
+            const int cp = ln.lr + LPR * v;
             const size_t o = (size_t)rl * g.ldp + (CL ? ln.cs[v] : ln.c[v]);
-            double2 p[LAZY];
-#pragma unroll
-            for (int j = 0; j < LAZY; ++j)
-                p[j] = CL ? ldn2(ring.p[j < cnt ? j : 0] + o)
-                          : (j < cnt ? ldn2(ring.p[j] + o) : make_double2(0.0, 0.0));
             double2 x = ldn2(X + o);
 #pragma unroll
-            for (int j = 0; j < LAZY; ++j) {
-                if (j < cnt) {
-                    x.x = fma(al[j][v].x, p[j].x, x.x);
-                    x.y = fma(al[j][v].y, p[j].y, x.y);
+            for (int h = 0; h < 2; ++h) {
+                double2 p[HALF];
+#pragma unroll
+                for (int j = 0; j < HALF; ++j) {
+                    const int jj = h * HALF + j;
+                    p[j] = CL ? ldn2(ring.p[jj < cnt ? jj : 0] + o)
+                              : (jj < cnt ? ldn2(ring.p[jj] + o) : make_double2(0.0, 0.0));
+                }
+#pragma unroll
+                for (int j = 0; j < HALF; ++j) {
+                    const int jj = h * HALF + j;
+                    if (jj < cnt) {
+                        const double2 a = cf[jj][cp];
+                        x.x = fma(a.x, p[j].x, x.x);
+                        x.y = fma(a.y, p[j].y, x.y);
+                    }
                 }
             }
             if (!CL || (row < sc.re && ln.ok[v])) stn2(X + o, x);
@@ -537,23 +551,24 @@ __global__ __launch_bounds__(BLOCK) void k_xflush(Geom g, int cnt, const double 
 // iterations j < cnt of the window, in order, P = D^-1 R_j + beta_j P and
 // X += alpha_j P, with the same fused multiply-adds as the direction update
 // and the X flush of the classic form; one pass over P and X per window of
-// up to LAZY_SR iterations.  The window's step lengths and betas of the
-// block's columns sit in LDS (LAZY_SR of each per column pair would not fit
+// up to LAZY iterations.  The window's step lengths and betas of the
+// block's columns sit in LDS (LAZY of each per column pair would not fit
 // in registers); the residuals are read eight at a time.
 template <int LPR, int NV>
 __global__ __launch_bounds__(BLOCK) void k_pflush(Geom g, int cnt, const double *__restrict__ alphas,
-                                                  const double *__restrict__ betas, RingSR ring,
+                                                  const double *__restrict__ betas,
+                                                  Ring<double> ring,
                                                   const double *__restrict__ dinv,
                                                   double *__restrict__ P,
                                                   double *__restrict__ X) {
     constexpr int CP = Lane<LPR, NV>::CW / 2;   // column pairs of the chunk
-    constexpr int HALF = LAZY_SR / 2;
-    __shared__ double2 cf[2][LAZY_SR][CP];
+    constexpr int HALF = LAZY / 2;
+    __shared__ double2 cf[2][LAZY][CP];
     Sched sc;
     if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;   // whole block
     Lane<LPR, NV> ln(g, sc.cc);
-    for (int i = threadIdx.x; i < 2 * LAZY_SR * CP; i += BLOCK) {
-        const int q = i / (LAZY_SR * CP), j = (i / CP) % LAZY_SR, cp = i % CP;
+    for (int i = threadIdx.x; i < 2 * LAZY * CP; i += BLOCK) {
+        const int q = i / (LAZY * CP), j = (i / CP) % LAZY, cp = i % CP;
         const int col = sc.cc * 2 * CP + 2 * cp;
         cf[q][j][cp] = (j < cnt && col < g.ldp)
                            ? ld2((q ? betas : alphas) + (size_t)j * g.ldp + col)
@@ -975,8 +990,16 @@ static_assert(kTiles[FLUSH_TILE].lpr == 32 && kTiles[FLUSH_TILE].nv == 2 &&
                   kTiles[FLUSH_TILE].front == 1,
               "flush geometry");
 
+template <class TP>
+void launch_xflush(int n, int ldp, hipStream_t s, int cnt, const double *alphas, Ring<TP> ring,
+                   double *X) {
+    const Geom g = make_geom(n, ldp, FLUSH_TILE);
+    hipLaunchKernelGGL((k_xflush<TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas, ring,
+                       X);
+}
+
 void launch_pflush(int n, int ldp, hipStream_t s, int cnt, const double *alphas,
-                   const double *betas, RingSR ring, const double *dinv, double *P, double *X) {
+                   const double *betas, Ring<double> ring, const double *dinv, double *P, double *X) {
     const Geom g = make_geom(n, ldp, FLUSH_TILE);
     hipLaunchKernelGGL((k_pflush<32, 2>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
                        betas, ring, dinv, P, X);
@@ -989,12 +1012,6 @@ void launch_pupdate(const Geom &g, hipStream_t s, const double *beta, const doub
                        R, P, Pout);
 }
 
-template <int LPR, int NV, class TP>
-void launch_xflush(const Geom &g, hipStream_t s, int cnt, const double *alphas, Ring<TP> ring,
-                   double *X) {
-    hipLaunchKernelGGL((k_xflush<LPR, NV, TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
-                       ring, X);
-}
 
 template <int LPR, int NV, class TR>
 void launch_residual(const Geom &g, hipStream_t s, const zi_system *sys, const int32_t *colmap,
@@ -1030,7 +1047,7 @@ __global__ void k_dinv(const double *d, const int32_t *perm, int32_t n, double *
 struct zi_solver_ws {
     int ldp = 0, nrt_cap = 0;
     double *X = nullptr, *R = nullptr, *Q = nullptr, *dinv = nullptr;
-    double *P[LAZY_SR] = {};   // search-direction ring (classic: 0..7); lazy P and residual ring
+    double *P[LAZY] = {};   // search-direction ring (classic: 0..7); lazy P and residual ring
     double *aring = nullptr;                                  // LAZY x ldp step lengths
     double *aflush = nullptr;                                 // LAZY x ldp scratch
     double *bring = nullptr;                                  // LAZY x ldp betas (single-reduction)
@@ -1068,17 +1085,17 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
     ws->pool.cached = true;
     const size_t blk = (size_t)sys->n * ldp;
     zi_status st = ZI_OK;
-    for (int j = 0; j < LAZY_SR; ++j) {
+    for (int j = 0; j < LAZY; ++j) {
         if ((st = ws->pool.alloc(&ws->P[j], blk)) != ZI_OK) {
             delete ws;
             return st;
         }
     }
     if ((st = ws->pool.alloc(&ws->X, blk)) != ZI_OK || (st = ws->pool.alloc(&ws->R, blk)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->aring, (size_t)LAZY_SR * ldp)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->aflush, (size_t)LAZY_SR * ldp)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->bring, (size_t)LAZY_SR * ldp)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->bflush, (size_t)LAZY_SR * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->aring, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->aflush, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->bring, (size_t)LAZY * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->bflush, (size_t)LAZY * ldp)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->vs, (size_t)std::max<int64_t>(sys->sp_nnz, 1))) != ZI_OK ||
         (st = ws->pool.alloc(&ws->Q, blk)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->dinv, (size_t)sys->n)) != ZI_OK ||
@@ -1160,13 +1177,12 @@ struct SolveCtx {
     std::chrono::steady_clock::time_point t_start;
     template <class TP>
     TP *P(int k) const { return reinterpret_cast<TP *>(ws->P[k % LAZY]); }
-    int lazy() const { return sr ? LAZY_SR : LAZY; }
-    double *alpha(int k) const { return ws->aring + (size_t)(k % lazy()) * ldp; }
-    // Single-reduction form: residual r_k in a ring of LAZY_SR blocks (R,
+    double *alpha(int k) const { return ws->aring + (size_t)(k % LAZY) * ldp; }
+    // Single-reduction form: residual r_k in a ring of LAZY blocks (R,
     // P[1..15]; slot 0 is R, where the initial residual is formed), the lazy
     // search direction in P[0], S = A p in Q, the betas beside the step lengths.
-    double *Rsr(int k) const { return k % LAZY_SR == 0 ? ws->R : ws->P[k % LAZY_SR]; }
-    double *beta_slot(int k) const { return ws->bring + (size_t)(k % LAZY_SR) * ldp; }
+    double *Rsr(int k) const { return k % LAZY == 0 ? ws->R : ws->P[k % LAZY]; }
+    double *beta_slot(int k) const { return ws->bring + (size_t)(k % LAZY) * ldp; }
 };
 
 zi_status read_active(SolveCtx &c, hipStream_t s) {
@@ -1224,17 +1240,17 @@ zi_status enqueue_flush(SolveCtx &c, int it_end, hipStream_t s) {
     double *al = c.ws->aring;
     const int first = c.flushed % LAZY;
     {
-        Timed t(c, 3, s, cnt == LAZY && (it_end / LAZY) % (TIMING_STRIDE / LAZY) == 0);
+        Timed t(c, 3, s, cnt == LAZY);
         ZI_TRY(t.st);
         if (first == 0) {
-            ZI_TILE_SWITCH(c.tile, launch_xflush, c.g, s, cnt, (const double *)al, ring, c.ws->X);
+            launch_xflush<TP>(c.sys->n, c.ldp, s, cnt, (const double *)al, ring, c.ws->X);
         } else {
             // the step lengths are rotated into a contiguous scratch block
             for (int j = 0; j < cnt; ++j)
                 ZI_HIP(hipMemcpyAsync(c.ws->aflush + (size_t)j * c.ldp, c.alpha(c.flushed + j),
                                       sizeof(double) * c.ldp, hipMemcpyDeviceToDevice, s));
-            ZI_TILE_SWITCH(c.tile, launch_xflush, c.g, s, cnt, (const double *)c.ws->aflush, ring,
-                           c.ws->X);
+            launch_xflush<TP>(c.sys->n, c.ldp, s, cnt, (const double *)c.ws->aflush, ring,
+                              c.ws->X);
         }
     }
     ZI_HIP(hipGetLastError());
@@ -1290,10 +1306,10 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
 zi_status enqueue_flush_sr(SolveCtx &c, int it_end, hipStream_t s) {
     const int cnt = it_end - c.flushed;
     if (cnt <= 0) return ZI_OK;
-    RingSR ring;
-    for (int j = 0; j < LAZY_SR; ++j) ring.p[j] = c.Rsr(c.flushed + j);
+    Ring<double> ring;
+    for (int j = 0; j < LAZY; ++j) ring.p[j] = c.Rsr(c.flushed + j);
     const double *al = c.ws->aring, *bt = c.ws->bring;
-    if (c.flushed % LAZY_SR != 0) {   // rotate the coefficients into contiguous blocks
+    if (c.flushed % LAZY != 0) {   // rotate the coefficients into contiguous blocks
         for (int j = 0; j < cnt; ++j) {
             ZI_HIP(hipMemcpyAsync(c.ws->aflush + (size_t)j * c.ldp, c.alpha(c.flushed + j),
                                   sizeof(double) * c.ldp, hipMemcpyDeviceToDevice, s));
@@ -1304,7 +1320,7 @@ zi_status enqueue_flush_sr(SolveCtx &c, int it_end, hipStream_t s) {
         bt = c.ws->bflush;
     }
     {
-        Timed t(c, 2, s, cnt == LAZY_SR);
+        Timed t(c, 2, s, cnt == LAZY);
         ZI_TRY(t.st);
         launch_pflush(c.sys->n, c.ldp, s, cnt, al, bt, ring, (const double *)c.ws->dinv,
                       c.ws->P[0], c.ws->X);
@@ -1334,7 +1350,7 @@ zi_status enqueue_iteration_sr(SolveCtx &c, int k, hipStream_t s) {
                        (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q, ws->part[0]);
     }
     hipLaunchKernelGGL(k_red_alpha_sr, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt);
-    if ((k + 1) % LAZY_SR == 0) ZI_TRY(enqueue_flush_sr(c, k + 1, s));
+    if ((k + 1) % LAZY == 0) ZI_TRY(enqueue_flush_sr(c, k + 1, s));
     {
         Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
@@ -1474,12 +1490,11 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     c.L = L;
     c.maxit = o->maxit > 0 ? o->maxit : 50000;
     c.check = o->check_every > 0 ? o->check_every : 8;
-    c.check = ((c.check + LAZY - 1) / LAZY) * LAZY;
-    // a replayed graph chunk must end on an X flush (the single-reduction
-    // form flushes every LAZY_SR iterations; eager solves check every LAZY)
-    if (c.sr && graphs) c.check = ((c.check + LAZY_SR - 1) / LAZY_SR) * LAZY_SR;
+    c.check = ((c.check + CHECK_MIN - 1) / CHECK_MIN) * CHECK_MIN;
+    // a replayed graph chunk must end on an X flush (every LAZY iterations)
+    if (graphs) c.check = ((c.check + LAZY - 1) / LAZY) * LAZY;
     if (c.mixed) {   // a divisor of MIXED_REPLACE: captured chunks repeat per phase
-        int q = LAZY;
+        int q = graphs ? LAZY : CHECK_MIN;
         while (q < c.check && q < MIXED_REPLACE) q *= 2;
         c.check = q;
     }
@@ -1530,7 +1545,7 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
                                (const double *)ws->dinv, nnz, ws->vs);
         ZI_TRY(fill_f64(ws->Q, 0.0, (size_t)n * ldp, s));
         ZI_TRY(fill_f64(ws->P[0], 0.0, (size_t)n * ldp, s));
-        ZI_TRY(fill_f64(ws->bring, 0.0, (size_t)LAZY_SR * ldp, s));
+        ZI_TRY(fill_f64(ws->bring, 0.0, (size_t)LAZY * ldp, s));
     } else {
         ZI_TRY(enqueue_restart_direction(c, s));
     }
@@ -1621,7 +1636,7 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
             const int64_t bytes_sr[3] = {
                 abytes + 24 * ne + (int64_t)n * 8,         // read R; r/w S; D^-1
                 24 * ne + (int64_t)n * 8,                  // read R, S; write R; D^-1
-                (32 + LAZY_SR * 8) * ne + (int64_t)n * 8};   // r/w P, X; read LAZY_SR residuals
+                (32 + LAZY * 8) * ne + (int64_t)n * 8};   // r/w P, X; read LAZY residuals
             const char *const *names = c.sr ? names_sr : names_classic;
             const int64_t *bytes = c.sr ? bytes_sr : bytes_classic;
             st->n_kernels = c.sr ? 3 : 4;
@@ -1875,12 +1890,12 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     int bt = 0;
     double bms = 1e30;
     // Each tile is scored by one iteration's kernels: the SpMM, the residual
-    // update, the direction update (classic form) and 1/LAZY of the flush,
-    // each the best of three launches after a warm-up.
+    // update and the direction update (classic form), each the best of three
+    // launches after a warm-up (the X flushes run with their own geometry).
     for (int t = 0; t < NTILES; ++t) {
         const Geom g = make_geom(n, ldp, t);
         double total = 0.0;
-        const int kinds = precision == ZI_FP32_SPMM_IR ? 4 : 2;
+        const int kinds = precision == ZI_FP32_SPMM_IR ? 3 : 2;
         for (int kind = 0; kind < kinds; ++kind) {
             double tmin = 1e30;
             for (int rep = 0; rep < 4; ++rep) {
@@ -1890,8 +1905,6 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                     float *P1 = reinterpret_cast<float *>(ws->P[1]);
                     float *Qf = reinterpret_cast<float *>(ws->Q);
                     float *Rf = reinterpret_cast<float *>(ws->R);
-                    Ring<float> ring;
-                    for (int j = 0; j < LAZY; ++j) ring.p[j] = reinterpret_cast<float *>(ws->P[j]);
                     if (kind == 0) {
                         ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
                                        (const double *)sys->sp_val, (const float *)P0, Qf,
@@ -1900,13 +1913,10 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                         ZI_TILE_SWITCH(t, launch_update, g, s, (const double *)ws->aring,
                                        (const double *)ws->dinv, (const float *)Rf,
                                        (const float *)Qf, Rf, ws->part[1], ws->part[2]);
-                    } else if (kind == 2) {
+                    } else {
                         ZI_TILE_SWITCH(t, launch_pupdate, g, s, (const double *)ws->bring,
                                        (const double *)ws->dinv, (const float *)Rf,
                                        (const float *)P0, P1);
-                    } else {
-                        ZI_TILE_SWITCH(t, launch_xflush, g, s, LAZY, (const double *)ws->aring,
-                                       ring, ws->X);
                     }
                 } else {   // the FP64 solve's default (single-reduction) kernels
                     if (kind == 0) {
@@ -1928,10 +1938,7 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                 ZI_HIP(hipEventElapsedTime(&ms, e0, e1));
                 if (rep > 0) tmin = std::min(tmin, (double)ms);   // first run warms up
             }
-            // the classic form's X flush runs every LAZY iterations; the
-            // single-reduction flush has its own geometry and is not scored
-            const bool flush = precision == ZI_FP32_SPMM_IR && kind == kinds - 1;
-            total += flush ? tmin / LAZY : tmin;
+            total += tmin;   // the flushes have their own geometry: not scored
         }
         if (ms_out) ms_out[t] = total;
         if (total < bms) {
