@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="sphere2mm_L128")
     p.add_argument("--tile", type=int, default=-1)
@@ -141,20 +141,36 @@ def main():
     s0.close()
     torch.cuda.synchronize()
 
+    # Every library call synchronises its stream before returning, so the
+    # wall clock between calls splits a build into its stages without adding
+    # synchronisation.
+    stage_names = ("assemble", "transfer_solve", "leadfield", "destroy")
+
     def step():
+        t = [time.perf_counter()]
         s = zi.System(nodes, tets, sigma, tris, tre, H.Z)
+        t.append(time.perf_counter())
         _, st = s.transfer_solve(tol=1e-8, precond=a.precond, precision=a.precision,
                                  timing=True, tile=a.tile, out=T, columns=cols)
+        t.append(time.perf_counter())
         if cols is None:
             s.leadfield(T, G, out=LF)
+        t.append(time.perf_counter())
         s.close()
+        t.append(time.perf_counter())
+        st["stages"] = [t[i + 1] - t[i] for i in range(4)]
         return st
 
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = [step() for _ in range(a.steps)]
+    stats = []
+    step_s = []
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        stats.append(step())
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
 
@@ -247,6 +263,11 @@ def main():
                    "tile": stats[-1]["tile"], "columns_solved": K,
                    "leadfield": cols is None},
         "lf_build_s": dt,
+        "lf_build_s_median": float(np.median(step_s)),
+        "stages_median_s": {nm: float(np.median([x["stages"][i] for x in stats]))
+                            for i, nm in enumerate(stage_names)},
+        "electrode_solves_per_s_solve_only":
+            K / float(np.median([x["stages"][1] for x in stats])),
         "pcg_iters": {"median": int(np.median(iters)), "max": int(iters.max()),
                       "block_loop": int(stats[-1]["block_iters"]),
                       "refinements": int(stats[-1]["refinements"])},
