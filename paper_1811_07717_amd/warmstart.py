@@ -48,6 +48,18 @@ def _node_mean(H, values):
     return np.bincount(H.tets.ravel(), weights=np.repeat(values, 4), minlength=H.n) / cnt
 
 
+def _incidence(H):
+    """Node -> incident tets in ascending order, padded with -1 (n x max degree)."""
+    flat = H.tets.ravel().astype(np.int64)
+    order = np.argsort(flat, kind="stable")
+    cnt = np.bincount(flat, minlength=H.n)
+    start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    pos = np.arange(flat.size) - np.repeat(start, cnt)
+    inc = np.full((H.n, int(cnt.max())), -1, dtype=np.int64)
+    inc[flat[order], pos] = order // 4
+    return inc, cnt
+
+
 class WarmStart:
     def __init__(self, H, dims=(N_FEATURES, 64, 64, 64, 64, 64, 1), seed=0, log=print):
         import torch
@@ -67,7 +79,11 @@ class WarmStart:
         self.b_rows, self.b_col, self.b_val = rows, v["b_col"].long(), v["b_val"]
         self.static = torch.from_numpy(np.concatenate(
             [H.nodes / R, _node_mean(H, np.log(H.sigma / 0.33))[:, None]], axis=1)).cuda()
-        self.sig_ref_log = np.log(H.sigma)
+        inc, cnt = _incidence(H)
+        self.inc = torch.from_numpy(inc).cuda()
+        self.inc_valid = self.inc >= 0
+        self.inc_cnt = torch.from_numpy(cnt.astype(np.float64)).cuda()
+        self.sig_ref_log = torch.log(torch.from_numpy(H.sigma).cuda())
         self.net = zi.MeshGNN(self.base, self.dims)
         self.net.set_params(glorot_params(self.dims, seed, zero_last=True))
         self.gain = 1.0
@@ -75,6 +91,16 @@ class WarmStart:
     def close(self):
         self.net.close()
         self.base.close()
+
+    def log_perturbation(self, sigma):
+        """Per-node mean over the incident tets of log(sigma / sigma_ref), on the
+        device (sigma: per-tet conductivities, numpy or a device tensor)."""
+        torch = self.torch
+        sig = sigma if isinstance(sigma, torch.Tensor) else torch.from_numpy(sigma)
+        d = torch.log(sig.cuda()) - self.sig_ref_log
+        g = torch.where(self.inc_valid, d[self.inc.clamp(min=0)], torch.zeros((), dtype=d.dtype,
+                                                                               device=d.device))
+        return g.sum(dim=1) / self.inc_cnt
 
     def features(self, sigma, l, pert=None):
         torch = self.torch
@@ -86,7 +112,7 @@ class WarmStart:
         b[self.b_rows[sel]] = self.b_val[sel]
         X[:, 0] = b / b.abs().max()
         if pert is None:
-            pert = torch.from_numpy(_node_mean(H, np.log(sigma) - self.sig_ref_log)).cuda()
+            pert = self.log_perturbation(sigma)
         X[:, 1] = pert
         X[:, 2] = self.T0[:, l] / self.scale[l]
         X[:, 3:6] = self.static[:, 0:3]
@@ -100,7 +126,7 @@ class WarmStart:
 
     def predict_x0(self, sigma, ls):
         torch = self.torch
-        pert = torch.from_numpy(_node_mean(self.H, np.log(sigma) - self.sig_ref_log)).cuda()
+        pert = self.log_perturbation(sigma)
         cols = []
         for l in ls:
             y = self.net.forward(self.features(sigma, l, pert)).double()
@@ -114,14 +140,13 @@ class WarmStart:
         data = []
         t0 = time.time()
         for f in range(n_fields):
-            sig = hm.perturbed_sigma(self.H, seed=seed * 100003 + f)
-            s = zi.System(self.base._keep[0], self.base._keep[1],
-                          torch.from_numpy(sig).cuda(), self.base._keep[3],
+            sig = torch.from_numpy(hm.perturbed_sigma(self.H, seed=seed * 100003 + f)).cuda()
+            s = zi.System(self.base._keep[0], self.base._keep[1], sig, self.base._keep[3],
                           self.base._keep[4], self.H.Z)
             ls = rng.choice(self.H.L, size=per_field, replace=False)
             T, _ = s.transfer_solve(tol=1e-8, precision=precision, columns=ls, graph=True)
             s.close()
-            pert = torch.from_numpy(_node_mean(self.H, np.log(sig) - self.sig_ref_log)).cuda()
+            pert = self.log_perturbation(sig)
             for j, l in enumerate(ls):
                 data.append((self.features(sig, int(l), pert), self.target(T[:, j], int(l))))
             if (f + 1) % max(1, n_fields // 10) == 0:
@@ -159,9 +184,9 @@ class WarmStart:
         rng = np.random.default_rng(seed)
         rows = []
         for f in range(n_fields):
-            sig = hm.perturbed_sigma(self.H, seed=seed * 100003 + f)
-            s = zi.System(self.base._keep[0], self.base._keep[1], torch.from_numpy(sig).cuda(),
-                          self.base._keep[3], self.base._keep[4], self.H.Z)
+            sig = torch.from_numpy(hm.perturbed_sigma(self.H, seed=seed * 100003 + f)).cuda()
+            s = zi.System(self.base._keep[0], self.base._keep[1], sig, self.base._keep[3],
+                          self.base._keep[4], self.H.Z)
             l = int(rng.integers(self.H.L))
             res = {}
             for name in ("zero", "t0", "gnn"):
