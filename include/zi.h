@@ -205,7 +205,8 @@ zi_status zi_autotune(zi_system *sys, int32_t precision, int32_t *best_tile, dou
  *   G        n_nodes x n_cols in CSC form: g_colptr (n_cols + 1), g_rowind
  *            and g_val (g_colptr[n_cols] entries); the source matrix of
  *            App. A.1 (entries g_ij = int psi_i div w_j).
- *   LF       L x n_cols float64, row-major (electrode-major).
+ *   LF       L x n_cols float64, row-major (electrode-major).  n_cols may be
+ *            0: nothing is written, and LF and G's arrays may be NULL.
  *   precision ZI_FP64, or 1 for float32 matrix-core products (T^T G and the
  *            final product rounded to float32 inputs, float32 accumulation).
  * ZI_EBREAKDOWN if M = C - B^T T is not positive definite. */

@@ -139,7 +139,8 @@ zi_status zi_leadfield(const zi_system *sys, const double *T, int32_t n_cols,
                        const int32_t *g_colptr, const int32_t *g_rowind, const double *g_val,
                        double *LF, int32_t precision, void *hip_stream) {
     zi::g_err[0] = 0;
-    if (!sys || !T || !LF || n_cols < 0 || (n_cols > 0 && (!g_colptr || !g_rowind || !g_val))) {
+    if (!sys || !T || n_cols < 0 ||
+        (n_cols > 0 && (!LF || !g_colptr || !g_rowind || !g_val))) {
         set_error("null argument or negative n_cols");
         return ZI_EINVAL;
     }
@@ -159,8 +160,16 @@ zi_status zi_point_dipoles(const zi_system *sys, int32_t m, const int32_t *dipol
         set_error("too many dipoles");
         return ZI_EINVAL;
     }
-    ZI_GUARD(return zi_point_dipoles_impl(sys, m, dipole_tets, g_colptr, g_rowind, g_val,
-                                          (hipStream_t)hip_stream);)
+    ZI_GUARD({
+        const zi_status st = zi_point_dipoles_impl(sys, m, dipole_tets, g_colptr, g_rowind,
+                                                   g_val, (hipStream_t)hip_stream);
+        if (st != ZI_OK) return st;
+        if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) {
+            set_error("hipStreamSynchronize failed");
+            return ZI_EDEVICE;
+        }
+        return ZI_OK;
+    })
 }
 
 zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y, int32_t tile,

@@ -167,3 +167,18 @@ def test_pcg_form_options(head):
     _, st = g.transfer_solve(tol=1e-8, precision="fp32_spmm_ir", form="classic")
     assert st["status"] == zi.ZI_OK
     g.close()
+
+
+def test_empty_source_matrix_and_no_dipoles(head):
+    # Degenerate sizes: a source matrix with no columns gives an L x 0 lead
+    # field, and zero dipoles give the column pointer [0].
+    g = build(head)
+    T, _ = g.transfer_solve(tol=1e-8)
+    cp = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ri = torch.empty(0, dtype=torch.int32, device="cuda")
+    gv = torch.empty(0, dtype=torch.float64, device="cuda")
+    LF = g.leadfield(T, (cp, ri, gv))
+    assert tuple(LF.shape) == (head.L, 0)
+    cp0, ri0, gv0 = g.point_dipoles(torch.empty(0, dtype=torch.int32, device="cuda"))
+    assert cp0.tolist() == [0] and ri0.numel() == 0 and gv0.numel() == 0
+    g.close()
