@@ -1185,17 +1185,27 @@ struct SolveCtx {
     double *beta_slot(int k) const { return ws->bring + (size_t)(k % LAZY) * ldp; }
 };
 
-zi_status read_active(SolveCtx &c, hipStream_t s) {
-    // active (ldp) and flag are adjacent; one copy into pinned memory
+// The active flags (ldp) and the breakdown flag are adjacent: one copy into
+// the workspace's pinned buffer, read after the stream has been synchronised.
+zi_status enqueue_read_active(SolveCtx &c, hipStream_t s) {
     ZI_HIP(hipMemcpyAsync(c.ws->h_pin, c.sc.active, sizeof(int32_t) * (c.ldp + 1),
                           hipMemcpyDeviceToHost, s));
-    ZI_HIP(hipStreamSynchronize(s));
+    return ZI_OK;
+}
+
+void take_active(SolveCtx &c) {
     c.h_flag = c.ws->h_pin[c.ldp];
     c.any_active = false;
     for (int k = 0; k < c.ldp; ++k) {
         c.h_active[k] = c.ws->h_pin[k];
         c.any_active = c.any_active || c.h_active[k];
     }
+}
+
+zi_status read_active(SolveCtx &c, hipStream_t s) {
+    ZI_TRY(enqueue_read_active(c, s));
+    ZI_HIP(hipStreamSynchronize(s));
+    take_active(c);
     return ZI_OK;
 }
 
@@ -1576,15 +1586,19 @@ zi_status solve_after_converged(SolveCtx &c, hipStream_t s) {
     return enqueue_restart_direction(c, s);
 }
 
-// Host check after a chunk of iterations.
-zi_status solve_check(SolveCtx &c, hipStream_t s) {
-    ZI_TRY(read_active(c, s));
+// Host check after a chunk, once the active flags have been taken.
+zi_status solve_check_taken(SolveCtx &c, hipStream_t s) {
     if (c.h_flag || c.it >= c.maxit) {
         c.done = true;
         return ZI_OK;
     }
     if (!c.any_active) return solve_after_converged(c, s);
     return ZI_OK;
+}
+
+zi_status solve_check(SolveCtx &c, hipStream_t s) {
+    ZI_TRY(read_active(c, s));
+    return solve_check_taken(c, s);
 }
 
 zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
@@ -1840,10 +1854,22 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
             r = ZI_EDEVICE;
             break;
         }
+        // every member's flags in one synchronisation
         for (int k : members) {
             cs[k].it += chunk;
             cs[k].flushed = cs[k].it;
-            r = solve_check(cs[k], s);
+            r = enqueue_read_active(cs[k], s);
+            if (r != ZI_OK) break;
+        }
+        if (r != ZI_OK) break;
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            set_error("hipStreamSynchronize failed");
+            r = ZI_EDEVICE;
+            break;
+        }
+        for (int k : members) {
+            take_active(cs[k]);
+            r = solve_check_taken(cs[k], s);
             if (r != ZI_OK) break;
         }
         if (r != ZI_OK) break;
