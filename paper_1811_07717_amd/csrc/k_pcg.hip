@@ -1806,18 +1806,29 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
         ZI_TRY(solve_begin(systems[k], o, cs[k], s, true));
         cs[k].timing = false;   // events cannot be captured
     }
-    std::vector<hipStream_t> streams(nsys + 1);   // one per system + capture origin
+    // Heads are captured in groups of BATCH_GROUP: when a head finishes, only
+    // its group's graph is captured again.  Each group's graph is launched on
+    // a stream of its own, forked from and joined back to the caller's stream.
+    constexpr int BATCH_GROUP = 8;
+    const int ngroups = (nsys + BATCH_GROUP - 1) / BATCH_GROUP;
+    // one stream per system (capture branches), per group (launch) + capture origin
+    std::vector<hipStream_t> streams(nsys + ngroups + 1);
     for (auto &x : streams) ZI_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    hipStream_t cap = streams[nsys];
-    struct StreamGuard {
+    std::vector<hipEvent_t> events(ngroups + 1);   // joins, fork
+    for (auto &e : events) ZI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipStream_t cap = streams[nsys + ngroups];
+    struct Guard {
         std::vector<hipStream_t> &v;
-        ~StreamGuard() {
+        std::vector<hipEvent_t> &e;
+        ~Guard() {
             for (auto x : v) (void)hipStreamDestroy(x);
+            for (auto x : e) (void)hipEventDestroy(x);
         }
-    } guard{streams};
+    } guard{streams, events};
     const int chunk = cs[0].check;   // same options for every system
-    GraphSet gs;
-    std::vector<int> members, last;
+    std::vector<GraphSet> gsets(ngroups);
+    std::vector<std::vector<int>> last(ngroups);
+    std::vector<int> members, gm;
     zi_status r = ZI_OK;
     for (;;) {
         members.clear();
@@ -1834,26 +1845,40 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
             }
         }
         if (r != ZI_OK || members.empty()) break;
-        if (members != last) {   // members share the iteration count (and phase)
-            gs.reset(cs[members[0]]);
-            last = members;
-        }
-        hipGraphExec_t &exec = gs.ex[GraphSet::phase(cs[members[0]])];
-        if (!exec) {
-            std::vector<SolveCtx *> sel;
-            std::vector<hipStream_t> ss;
-            for (int k : members) {
-                sel.push_back(&cs[k]);
-                ss.push_back(streams[k]);
-            }
-            r = capture_graph(sel, ss, chunk, cap, &exec);
-            if (r != ZI_OK) break;
-        }
-        if (hipGraphLaunch(exec, s) != hipSuccess) {
-            set_error("hipGraphLaunch failed");
+        if (hipEventRecord(events[ngroups], s) != hipSuccess) {
             r = ZI_EDEVICE;
             break;
         }
+        for (int grp = 0; grp < ngroups && r == ZI_OK; ++grp) {
+            gm.clear();
+            for (int k : members)
+                if (k / BATCH_GROUP == grp) gm.push_back(k);
+            if (gm.empty()) continue;
+            if (gm != last[grp]) {   // members share the iteration count (and phase)
+                gsets[grp].reset(cs[gm[0]]);
+                last[grp] = gm;
+            }
+            hipGraphExec_t &exec = gsets[grp].ex[GraphSet::phase(cs[gm[0]])];
+            if (!exec) {
+                std::vector<SolveCtx *> sel;
+                std::vector<hipStream_t> ss;
+                for (int k : gm) {
+                    sel.push_back(&cs[k]);
+                    ss.push_back(streams[k]);
+                }
+                r = capture_graph(sel, ss, chunk, cap, &exec);
+                if (r != ZI_OK) break;
+            }
+            hipStream_t ls = streams[nsys + grp];
+            if (hipStreamWaitEvent(ls, events[ngroups], 0) != hipSuccess ||
+                hipGraphLaunch(exec, ls) != hipSuccess ||
+                hipEventRecord(events[grp], ls) != hipSuccess ||
+                hipStreamWaitEvent(s, events[grp], 0) != hipSuccess) {
+                set_error("hipGraphLaunch failed");
+                r = ZI_EDEVICE;
+            }
+        }
+        if (r != ZI_OK) break;
         // every member's flags in one synchronisation
         for (int k : members) {
             cs[k].it += chunk;
@@ -1874,7 +1899,7 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
         }
         if (r != ZI_OK) break;
     }
-    gs.clear();
+    for (auto &g : gsets) g.clear();
     ZI_TRY(r);
     zi_status worst = ZI_OK;
     for (int k = 0; k < nsys; ++k) {
