@@ -177,9 +177,10 @@ zi_status zi_transfer_solve(zi_system *sys, const zi_solve_opts *opts, double *T
 
 /* Transfer matrices of several systems (e.g. many head models) at once.
  * Each system runs exactly the iteration of zi_transfer_solve; the
- * iterations of all systems that are still active are captured into one
- * hipGraph (one branch per system, check_every iterations per replay) that is
- * replayed until every system has converged.  opts applies to every system
+ * iterations of the systems that are still active are captured into hipGraphs
+ * (one per group of eight systems, one branch per system, check_every
+ * iterations per replay; a group is captured again when one of its systems
+ * finishes) that are replayed until every system has converged.  opts applies to every system
  * (x0 must be NULL); T[k] is n_nodes(k) x L(k); stats may be NULL or an array
  * of n_systems.  Returns the first non-OK status of the systems (all T are
  * written). */
