@@ -131,6 +131,11 @@ typedef struct {
     int32_t n_columns;
     int32_t form;        /* ZI_PCG_AUTO, ZI_PCG_CLASSIC or ZI_PCG_SINGLE
                             (ZI_PCG_SINGLE with ZI_FP32_SPMM_IR: ZI_EINVAL) */
+    double refine_eta;   /* ZI_FP32_SPMM_IR: each float32 cycle stops once it has
+                            reduced its starting residual by this factor (or
+                            reached tol), then an FP64 refinement step restarts
+                            the columns that miss tol; 0 -> run every cycle to
+                            tol.  In [0, 1), else ZI_EINVAL; ignored in ZI_FP64 */
 } zi_solve_opts;
 
 /* Statistics of zi_transfer_solve.  The HOST arrays are caller-owned, length

@@ -1510,7 +1510,11 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     }
     c.tol = o->tol > 0 ? o->tol : 1e-8;
     c.tol2 = c.tol * c.tol;
-    c.eta2 = 0.0;
+    if (!(o->refine_eta >= 0.0 && o->refine_eta < 1.0)) {
+        set_error("refine_eta must be in [0, 1) (got %g)", o->refine_eta);
+        return ZI_EINVAL;
+    }
+    c.eta2 = c.mixed ? o->refine_eta * o->refine_eta : 0.0;
     c.timing = o->timing != 0 && o->graph == 0;
     c.timer = EventTimer{&ws->ev};
     c.h_active.assign(ldp, 0);

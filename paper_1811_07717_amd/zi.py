@@ -43,7 +43,8 @@ class ZiSolveOpts(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("graph", ctypes.c_int32), ("x0", ctypes.c_void_p),
-                ("columns", c_i32p), ("n_columns", ctypes.c_int32), ("form", ctypes.c_int32)]
+                ("columns", c_i32p), ("n_columns", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("refine_eta", ctypes.c_double)]
 
 
 class ZiSolveStats(ctypes.Structure):
@@ -245,7 +246,8 @@ class System:
     # -- solve ---------------------------------------------------------------
     def transfer_solve(self, tol=1e-8, maxit=0, precond="jacobi", precision="fp64",
                        check_every=0, timing=False, tile=-1, x0=None, out=None,
-                       raise_on_error=True, graph=False, columns=None, form="auto"):
+                       raise_on_error=True, graph=False, columns=None, form="auto",
+                       refine_eta=0.0):
         import torch
         cols = None if columns is None else np.ascontiguousarray(np.asarray(columns,
                                                                             dtype=np.int32))
@@ -263,7 +265,7 @@ class System:
                         int(check_every), int(bool(timing)), int(tile), int(bool(graph)),
                         _dev(x0, torch.float64, "x0") if x0 is not None else None,
                         cols.ctypes.data_as(c_i32p) if cols is not None else None,
-                        nc if cols is not None else 0, PCG_FORM[form])
+                        nc if cols is not None else 0, PCG_FORM[form], float(refine_eta))
         rc = lib().zi_transfer_solve(self._h, ctypes.byref(o), _dev(T, torch.float64, "T"),
                                      ctypes.byref(st), _stream())
         stats = dict(iters=iters, relres_rec=rec, relres_true=true, seconds=st.seconds,
