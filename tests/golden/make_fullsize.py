@@ -27,6 +27,8 @@ from oracle import fem, leadfield as lf, solve, source  # noqa: E402
 from paper_1811_07717_amd import headmodel as hm  # noqa: E402
 
 LF_COLUMNS = [0, 3 * 1234 + 1, 3 * 5000 + 2, 3 * 7777, 3 * 9000 + 1, 29999]
+# the 1 mm workload has 100 000 dipoles: columns spread over all of them
+LF_COLUMNS_1MM = [0, 3 * 1234 + 1, 3 * 31415 + 2, 3 * 50000, 3 * 77777 + 1, 299999]
 PCG_COLUMNS = [0, 77]
 
 
@@ -49,7 +51,8 @@ def main(name="sphere2mm_L128"):
         its[str(c)] = int(k)
         print("pcg column", c, k, time.time() - t0, flush=True)
     G = source.point_dipole_matrix(H.nodes, H.tets, H.dipole_tets)
-    cols = [c for c in LF_COLUMNS if c < G.shape[1]]
+    wanted = LF_COLUMNS_1MM if G.shape[1] >= 300000 else LF_COLUMNS
+    cols = [c for c in wanted if c < G.shape[1]]
     LFc = lf.leadfield_columns_reciprocity(A, S["B"], S["C"], G[:, cols], tol=1e-12)
     print("lead-field columns", time.time() - t0, flush=True)
     out = {
