@@ -221,6 +221,27 @@ zi_status zi_leadfield(const zi_system *sys, const double *T, int32_t n_cols,
                        const double *g_val, double *LF, int32_t precision,
                        void *hip_stream);
 
+/* zi_leadfield without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as zi_leadfield; the
+ * lead field is the same to the bit.
+ *   Workspace: a fixed 16 MiB array per device, set up on the first call on
+ *   that device and held until the process ends.  It holds the four L x L
+ *   matrices of the Schur step and Pt for zi_leadfield_noalloc_max_cols(L)
+ *   columns of G at a time; longer G are processed in column chunks.
+ *   Limits: L <= 256 (ZI_EINVAL otherwise), any n_cols.
+ *   Calls that overlap on one device share the array and race: serialise
+ *   them (one stream, or one call at a time per device).
+ *   No hipMalloc, hipFree or allocating library routine is called. */
+zi_status zi_leadfield_noalloc(const zi_system *sys, const double *T, int32_t n_cols,
+                               const int32_t *g_colptr, const int32_t *g_rowind,
+                               const double *g_val, double *LF, int32_t precision,
+                               void *hip_stream);
+
+/* Columns of G per chunk in zi_leadfield_noalloc for L electrodes (0 if L is
+ * outside [1, 256]). */
+int64_t zi_leadfield_noalloc_max_cols(int32_t n_electrodes);
+
 /* Source matrix of point dipoles (Sec. 2 "Primary current model", read as
  * the partial-integration dipole): a unit dipole along axis k at the centroid
  * of tet d gives column 3 j + k with G[i, 3 j + k] = -d psi_i / d x_k on that

@@ -6,7 +6,9 @@
 //   gemm    LF = W Pt^T on the matrix cores (v_mfma_f64_16x16x4f64, or the
 //           float32 variant), each wave owning 16 output columns and every
 //           electrode row so that a Pt row is read once per wave.
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "zi_internal.h"
 
@@ -269,7 +271,8 @@ __device__ __forceinline__ void gemm_tile(const double *W, const double *Pt, int
 
 template <int MT>
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f64(const double *W, const double *Pt,
-                                                           int L, int n_cols, double *LF) {
+                                                           int L, int n_cols, int64_t ldlf,
+                                                           double *LF) {
     __shared__ double Ws[2][MT * 16][gk<MT>() + 1];
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = blockIdx.x * 64 + wv * 16 + (t & 15);
@@ -289,13 +292,14 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f64(const double *W, cons
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = m * 16 + kq + 4 * i;   // f64 result layout
-            if (row < L) LF[(size_t)row * n_cols + col] = acc[m][i];
+            if (row < L) LF[(size_t)row * ldlf + col] = acc[m][i];
         }
 }
 
 template <int MT>
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f32(const double *W, const double *Pt,
-                                                           int L, int n_cols, double *LF) {
+                                                           int L, int n_cols, int64_t ldlf,
+                                                           double *LF) {
     __shared__ double Ws[2][MT * 16][gk<MT>() + 1];
     const int t = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = blockIdx.x * 64 + wv * 16 + (t & 15);
@@ -315,7 +319,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f32(const double *W, cons
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = m * 16 + 4 * kq + i;   // f32 result layout
-            if (row < L) LF[(size_t)row * n_cols + col] = (double)acc[m][i];
+            if (row < L) LF[(size_t)row * ldlf + col] = (double)acc[m][i];
         }
 }
 
@@ -427,50 +431,35 @@ zi_status zi_eit_source_impl(const zi_system *sys, const double *T, int32_t P, c
     return ZI_OK;
 }
 
-zi_status zi_leadfield_impl(const zi_system *csys, const double *T, int32_t n_cols,
-                            const int32_t *cp, const int32_t *ri, const double *gv, double *LF,
-                            int32_t precision, hipStream_t s) {
-    zi_system *sys = const_cast<zi_system *>(csys);
+namespace {
+
+// Workspace of one lead-field evaluation: the L x L matrices of the Schur
+// complement step, the flag word, and Pt for up to pt_cols columns of G.
+struct LfWork {
+    double *S, *Lf, *Minv, *W, *Pt;
+    int *flag;
+    int64_t pt_cols;
+};
+
+zi_status leadfield_core(const zi_system *sys, const double *T, int32_t n_cols,
+                         const int32_t *cp, const int32_t *ri, const double *gv, double *LF,
+                         int32_t precision, const LfWork &w, hipStream_t s) {
     const int L = sys->L;
-    if (L > 256) {
-        set_error("zi_leadfield supports at most 256 electrodes (got %d)", L);
-        return ZI_EINVAL;
-    }
-    if (precision != 0 && precision != 1) {
-        set_error("unknown lead-field precision %d", precision);
-        return ZI_EINVAL;
-    }
-    Pool tmp;
-    double *S = nullptr, *Lf = nullptr, *Minv = nullptr;
-    int *flag = nullptr;
-    ZI_TRY(tmp.alloc(&S, (size_t)L * L));
-    ZI_TRY(tmp.alloc(&Lf, (size_t)L * L));
-    ZI_TRY(tmp.alloc(&Minv, (size_t)L * L));
-    ZI_TRY(tmp.alloc(&flag, 1));
-    if (!sys->W) ZI_TRY(sys->pool.alloc(&sys->W, (size_t)L * L));
-    const size_t need = (size_t)n_cols * L;
-    if (need > sys->Pt_cap) {
-        if (sys->Pt) (void)hipFree(sys->Pt);
-        sys->Pt = nullptr;
-        sys->Pt_cap = 0;
-        ZI_HIP(hipMalloc(&sys->Pt, need * sizeof(double)));
-        sys->Pt_cap = need;
-    }
-    ZI_TRY(fill_i32(flag, 0, 1, s));
+    ZI_TRY(fill_i32(w.flag, 0, 1, s));
     int hflag = 0;
     if (n_cols > 0) {
         hipLaunchKernelGGL(k_check_colptr, dim3(grid_for((size_t)n_cols + 1, 256)), dim3(256), 0,
-                           s, cp, n_cols, flag);
+                           s, cp, n_cols, w.flag);
         ZI_HIP(hipGetLastError());
         int32_t gnnz = 0;
         ZI_HIP(hipMemcpyAsync(&gnnz, cp + n_cols, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        ZI_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        ZI_HIP(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
         ZI_HIP(hipStreamSynchronize(s));
         if (!hflag && gnnz > 0) {
             hipLaunchKernelGGL(k_check_rowind, dim3(grid_for(gnnz, 256)), dim3(256), 0, s, ri,
-                               gnnz, sys->n, flag);
+                               gnnz, sys->n, w.flag);
             ZI_HIP(hipGetLastError());
-            ZI_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+            ZI_HIP(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
             ZI_HIP(hipStreamSynchronize(s));
         }
         if (hflag) {
@@ -479,26 +468,128 @@ zi_status zi_leadfield_impl(const zi_system *csys, const double *T, int32_t n_co
         }
     }
     hipLaunchKernelGGL(k_schur, dim3(L), dim3(64), 0, s, sys->e_ptr, sys->e_item, sys->b_row,
-                       sys->b_val, sys->C, T, L, S);
-    launch_chol(S, L, Lf, Minv, sys->W, flag, s);
+                       sys->b_val, sys->C, T, L, w.S);
+    launch_chol(w.S, L, w.Lf, w.Minv, w.W, w.flag, s);
     ZI_HIP(hipGetLastError());
-    if (n_cols > 0) {
-        hipLaunchKernelGGL(k_gather, dim3(grid_for((size_t)n_cols * 64, 256)), dim3(256), 0, s, cp,
-                           ri, gv, n_cols, T, L, sys->Pt);
-        const int mt = (L + 15) / 16;
-        const dim3 grid(grid_for(n_cols, 64)), block(GEMM_THREADS);
+    // columns in chunks of at most pt_cols: the gather of a chunk, then its
+    // product into columns [c0, c0 + nc) of LF (leading dimension n_cols)
+    const int mt = (L + 15) / 16;
+    for (int64_t c0 = 0; c0 < n_cols; c0 += w.pt_cols) {
+        const int nc = (int)std::min<int64_t>(w.pt_cols, n_cols - c0);
+        hipLaunchKernelGGL(k_gather, dim3(grid_for((size_t)nc * 64, 256)), dim3(256), 0, s,
+                           cp + c0, ri, gv, nc, T, L, w.Pt);
+        const dim3 grid(grid_for(nc, 64)), block(GEMM_THREADS);
         if (precision == 0) {
-            ZI_GEMM_SWITCH(k_gemm_f64, mt, grid, block, 0, s, sys->W, sys->Pt, L, n_cols, LF);
+            ZI_GEMM_SWITCH(k_gemm_f64, mt, grid, block, 0, s, w.W, w.Pt, L, nc,
+                           (int64_t)n_cols, LF + c0);
         } else {
-            ZI_GEMM_SWITCH(k_gemm_f32, mt, grid, block, 0, s, sys->W, sys->Pt, L, n_cols, LF);
+            ZI_GEMM_SWITCH(k_gemm_f32, mt, grid, block, 0, s, w.W, w.Pt, L, nc,
+                           (int64_t)n_cols, LF + c0);
         }
         ZI_HIP(hipGetLastError());
     }
-    ZI_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(&hflag, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
     ZI_HIP(hipStreamSynchronize(s));
     if (hflag) {
         set_error("M = C - B^T T is not positive definite");
         return ZI_EBREAKDOWN;
     }
     return ZI_OK;
+}
+
+zi_status leadfield_args(const zi_system *sys, int32_t precision) {
+    if (sys->L > 256) {
+        set_error("zi_leadfield supports at most 256 electrodes (got %d)", sys->L);
+        return ZI_EINVAL;
+    }
+    if (precision != 0 && precision != 1) {
+        set_error("unknown lead-field precision %d", precision);
+        return ZI_EINVAL;
+    }
+    return ZI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Lead field without device allocation.  The workspace lives in `scratch`, a
+// fixed array of every device the library runs on; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_DOUBLES = (size_t)2 << 20;   // 16 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES] = {};
+
+zi_status scratch_for_current_device(double **out) {
+    int dev = -1;
+    ZI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_error("device index %d out of range", dev);
+        return ZI_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return ZI_EDEVICE;
+        }
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return ZI_OK;
+}
+
+}  // namespace
+
+int64_t zi_leadfield_noalloc_max_cols_impl(int32_t L) {
+    if (L < 1 || L > 256) return 0;
+    const size_t mat = (size_t)L * L;
+    return (int64_t)((NOALLOC_DOUBLES - 4 * mat - 32) / (size_t)L);
+}
+
+zi_status zi_leadfield_noalloc_impl(const zi_system *sys, const double *T, int32_t n_cols,
+                                    const int32_t *cp, const int32_t *ri, const double *gv,
+                                    double *LF, int32_t precision, hipStream_t s) {
+    ZI_TRY(leadfield_args(sys, precision));
+    double *base = nullptr;
+    ZI_TRY(scratch_for_current_device(&base));
+    const size_t mat = (size_t)sys->L * sys->L;
+    LfWork w;
+    w.S = base;
+    w.Lf = base + mat;
+    w.Minv = base + 2 * mat;
+    w.W = base + 3 * mat;
+    w.flag = reinterpret_cast<int *>(base + 4 * mat);
+    w.Pt = base + 4 * mat + 32;
+    w.pt_cols = zi_leadfield_noalloc_max_cols_impl(sys->L);
+    return leadfield_core(sys, T, n_cols, cp, ri, gv, LF, precision, w, s);
+}
+
+zi_status zi_leadfield_impl(const zi_system *csys, const double *T, int32_t n_cols,
+                            const int32_t *cp, const int32_t *ri, const double *gv, double *LF,
+                            int32_t precision, hipStream_t s) {
+    zi_system *sys = const_cast<zi_system *>(csys);
+    ZI_TRY(leadfield_args(sys, precision));
+    const int L = sys->L;
+    Pool tmp;
+    LfWork w;
+    ZI_TRY(tmp.alloc(&w.S, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&w.Lf, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&w.Minv, (size_t)L * L));
+    ZI_TRY(tmp.alloc(&w.flag, 1));
+    if (!sys->W) ZI_TRY(sys->pool.alloc(&sys->W, (size_t)L * L));
+    w.W = sys->W;
+    const size_t need = (size_t)n_cols * L;
+    if (need > sys->Pt_cap) {
+        if (sys->Pt) (void)hipFree(sys->Pt);
+        sys->Pt = nullptr;
+        sys->Pt_cap = 0;
+        ZI_HIP(hipMalloc(&sys->Pt, need * sizeof(double)));
+        sys->Pt_cap = need;
+    }
+    w.Pt = sys->Pt;
+    w.pt_cols = std::max<int64_t>(n_cols, 1);
+    return leadfield_core(sys, T, n_cols, cp, ri, gv, LF, precision, w, s);
 }

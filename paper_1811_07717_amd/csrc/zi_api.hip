@@ -148,6 +148,24 @@ zi_status zi_leadfield(const zi_system *sys, const double *T, int32_t n_cols,
                                       (hipStream_t)hip_stream);)
 }
 
+zi_status zi_leadfield_noalloc(const zi_system *sys, const double *T, int32_t n_cols,
+                               const int32_t *g_colptr, const int32_t *g_rowind,
+                               const double *g_val, double *LF, int32_t precision,
+                               void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!sys || !T || n_cols < 0 ||
+        (n_cols > 0 && (!LF || !g_colptr || !g_rowind || !g_val))) {
+        set_error("null argument or negative n_cols");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_leadfield_noalloc_impl(sys, T, n_cols, g_colptr, g_rowind, g_val, LF,
+                                              precision, (hipStream_t)hip_stream);)
+}
+
+int64_t zi_leadfield_noalloc_max_cols(int32_t n_electrodes) {
+    return zi_leadfield_noalloc_max_cols_impl(n_electrodes);
+}
+
 zi_status zi_point_dipoles(const zi_system *sys, int32_t m, const int32_t *dipole_tets,
                            int32_t *g_colptr, int32_t *g_rowind, double *g_val,
                            void *hip_stream) {

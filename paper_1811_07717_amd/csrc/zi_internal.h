@@ -215,6 +215,10 @@ zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double 
 zi_status zi_leadfield_impl(const zi_system *sys, const double *T, int32_t n_cols,
                             const int32_t *cp, const int32_t *ri, const double *gv,
                             double *LF, int32_t precision, hipStream_t s);
+zi_status zi_leadfield_noalloc_impl(const zi_system *sys, const double *T, int32_t n_cols,
+                                    const int32_t *cp, const int32_t *ri, const double *gv,
+                                    double *LF, int32_t precision, hipStream_t s);
+int64_t zi_leadfield_noalloc_max_cols_impl(int32_t L);
 zi_status zi_point_dipoles_impl(const zi_system *sys, int32_t m, const int32_t *dt,
                                 int32_t *cp, int32_t *ri, double *gv, hipStream_t s);
 zi_status zi_eit_columns_impl(const zi_system *sys, const double *U, int32_t P, int32_t ne,

@@ -86,6 +86,10 @@ SIGNATURES = [
     ("zi_leadfield", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    ("zi_leadfield_noalloc", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    ("zi_leadfield_noalloc_max_cols", ctypes.c_int64, [ctypes.c_int32]),
     ("zi_point_dipoles", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -301,18 +305,21 @@ class System:
                "zi_point_dipoles")
         return cp, ri, gv
 
-    def leadfield(self, T, G, precision=0, out=None):
+    def leadfield(self, T, G, precision=0, out=None, noalloc=False):
+        """zi_leadfield, or zi_leadfield_noalloc (no device allocation inside
+        the library; the output must then be passed as ``out`` by a caller
+        that cannot allocate)."""
         import torch
         cp, ri, gv = G
         ncols = int(cp.shape[0]) - 1
         LF = out if out is not None else torch.empty((self.L, ncols), dtype=torch.float64,
                                                      device="cuda")
-        _check(lib().zi_leadfield(self._h, _dev(T, torch.float64, "T"), ncols,
-                                  _dev(cp, torch.int32, "g_colptr"),
-                                  _dev(ri, torch.int32, "g_rowind"),
-                                  _dev(gv, torch.float64, "g_val"),
-                                  _dev(LF, torch.float64, "LF"), int(precision), _stream()),
-               "zi_leadfield")
+        fn, name = ((lib().zi_leadfield_noalloc, "zi_leadfield_noalloc") if noalloc
+                    else (lib().zi_leadfield, "zi_leadfield"))
+        _check(fn(self._h, _dev(T, torch.float64, "T"), ncols,
+                  _dev(cp, torch.int32, "g_colptr"), _dev(ri, torch.int32, "g_rowind"),
+                  _dev(gv, torch.float64, "g_val"), _dev(LF, torch.float64, "LF"),
+                  int(precision), _stream()), name)
         return LF
 
     def eit_source(self, T, I, elems=None):
