@@ -4,7 +4,7 @@ closed-form multilayer-sphere potential, on the first oracle run.
 The paper prints no accuracy figures for its lead fields, so these guards are
 measured, not quoted: mean RDM and mean |MAG-1| over 6 fixed dipoles x 3
 orientations at 32 Fibonacci electrodes, for a homogeneous sphere and for the
-four-layer sphere, at 8 mm and 4 mm.  Calls only the oracle and the seeded
+four-layer sphere, at 8 mm, 4 mm and 2 mm.  Calls only the oracle and the seeded
 input generator.
 
     python tests/golden/make_physics_guards.py
@@ -49,7 +49,7 @@ def main():
     out = {"_source": "tests/golden/make_physics_guards.py (oracle only)"}
     for case, sig in (("homogeneous", (0.33,) * 4), ("four_layer", hm.SIGMAS)):
         out[case] = {}
-        for h in (8.0, 4.0):
+        for h in (8.0, 4.0, 2.0):
             r, m = physics_errors(h, sig)
             out[case]["%d" % h] = {"rdm": r, "mag": m}
             print(case, h, r, m, flush=True)

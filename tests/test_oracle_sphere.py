@@ -131,15 +131,25 @@ def _guards_module():
 def test_oracle_converges_to_sphere_series(case):
     # The paper prints no accuracy figures, so this is a convergence check:
     # mean RDM and |MAG-1| over 18 lead-field columns must drop from 8 mm to
-    # 4 mm, and stay within the guards frozen from the first oracle run
-    # (tests/golden/physics_guards.json, written by make_physics_guards.py).
+    # 4 mm to 2 mm and stay within the guards frozen from the first oracle
+    # run (tests/golden/physics_guards.json, written by make_physics_guards.py).
+    # 8 and 4 mm are recomputed here; the 2 mm point (a 427 000-node oracle
+    # solve, minutes on one core) is the stored oracle value, and the GPU
+    # path recomputes it in test_gpu_physics.py.
     sig = (0.33,) * 4 if case == "homogeneous" else hm.SIGMAS
     with open(os.path.join(GOLDEN, "physics_guards.json")) as f:
         guards = json.load(f)[case]
     mod = _guards_module()
     e8 = mod.physics_errors(8.0, sig)
     e4 = mod.physics_errors(4.0, sig)
-    assert e4[0] < e8[0] and e4[1] < e8[1]
+    e2 = (guards["2"]["rdm"], guards["2"]["mag"])
+    assert e2[0] < e4[0] < e8[0] and e2[1] < e4[1] < e8[1]
     for h, e in (("8", e8), ("4", e4)):
         assert e[0] <= guards[h]["rdm"] * 1.05
         assert e[1] <= guards[h]["mag"] * 1.05
+    # the homogeneous sphere at 2 mm is within the survey's initial guard;
+    # the four-layer one resolves the 6 mm skull and 2 mm CSF only coarsely
+    if case == "homogeneous":
+        assert e2[0] <= 0.05
+    else:
+        assert e2[0] <= 0.15
