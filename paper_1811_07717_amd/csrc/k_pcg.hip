@@ -24,6 +24,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "zi_internal.h"
 
@@ -42,6 +43,7 @@ struct Geom {
     int P, B, U;          // front schedule: row parts, blocks per unit, units
     int nrt;              // partial-sum rows per column
     int nb, nb_pad;       // blocks (nb_pad: launched, a multiple of 8)
+    int cl2n;             // ceil(log2 n): terms per column of a dot product
 };
 
 // Rows a block visits: base = rs + first + j * stride (base < re); the block's
@@ -301,27 +303,79 @@ __device__ __forceinline__ void block_partials(const Geom &g, const Lane<LPR, NV
     }
 }
 
+// Dot products of the SpMM whose value does not depend on how rows are
+// grouped into partial sums (the tile, the block that took a row).  Every
+// term t is pre-rounded on two fixed grids (the extraction of Demmel and
+// Nguyen's reproducible summation): with a per-column bound on the sum of
+// |t| (2^e >= bound), m1 = 1.5 2^(e+1) and m2 = m1 2^(ceil(log2 n)-52),
+// q1 = (m1 + t) - m1 is t on the grid ulp(m1), q2 = (m2 + r) - m2 the rest
+// r = t - q1 on the grid ulp(m2).  Sums of up to n such values stay exact in
+// FP64, so the two fold sums are the same in any order; the dot is their sum.
+// The dropped remainder is at most n ulp(m2) / 2 = 2^-60 bound for n <= 2^22.
+__device__ __forceinline__ double fold_grid(double bound) {
+    int e = 0;
+    (void)frexp(bound > 1e-280 ? bound : 1e-280, &e);   // bound <= 2^e
+    return ldexp(1.5, e + 1);
+}
+
+// m2 = m1 f2 with f2 = 2^(ceil(log2 n) - 52), the same for every column.
+__device__ __forceinline__ void fold_add(double u, double v, double m1, double f2, double &s1,
+                                         double &s2) {
+#pragma clang fp contract(off)
+    const double t = u * v;
+    const double m2 = m1 * f2;
+    const double q1 = (m1 + t) - m1;
+    const double r = t - q1;
+    const double q2 = (m2 + r) - m2;
+    s1 = s1 + q1;
+    s2 = s2 + q2;
+}
+
+// The rows a block's lanes process, calling f(row) for each: rows base + slot
+// with base = rs + first + j stride.
+template <int LPR, int NV, class F>
+__device__ __forceinline__ void for_rows(const Sched &sc, const Lane<LPR, NV> &ln, F &&f) {
+    for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
+        const int row = base + ln.slot;
+        if (row < sc.re) f(row);
+    }
+}
+
 // ---------------------------------------------------------------------------
 
 // Y = A X; with WITH_DOT also the partials of sum_i X[i,c] Y[i,c] (in FP64,
 // with Y as stored).
+// Three waves per SIMD for the SpMMs of up to two column pairs per lane (the
+// gathers need waves in flight more than registers).
+template <int NV>
+constexpr int spmm_waves() { return NV <= 2 ? 3 : 1; }
+
 template <int LPR, int NV, class TV, class TX, bool WITH_DOT>
-__global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(spmm_waves<NV>())))
+void k_spmm(Geom g, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ ci,
                                                 const TV *__restrict__ va,
                                                 const TX *__restrict__ X, TX *__restrict__ Y,
-                                                double *part) {
+                                                double *part, const double *__restrict__ bound) {
     using AT = typename Acc<TV>::type;
     using XT = typename Acc<TX>::type;
     Sched sc;
     if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
     Lane<LPR, NV> ln(g, sc.cc);
-    double2 dotacc[1][NV];
+    constexpr int CW = Lane<LPR, NV>::CW;
+    __shared__ double m1[WITH_DOT ? CW : 1];   // first fold grid of the chunk's columns
+    double2 dotacc[2][NV];                     // the two fold sums
+    const double f2 = ldexp(1.0, g.cl2n - 52);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) dotacc[0][v] = make_double2(0.0, 0.0);
-    for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
-        const int row = base + ln.slot;
-        if (row >= sc.re) continue;
+    for (int v = 0; v < NV; ++v) dotacc[0][v] = dotacc[1][v] = make_double2(0.0, 0.0);
+    if (WITH_DOT) {
+        for (int i = threadIdx.x; i < CW; i += BLOCK) {
+            const int col = sc.cc * CW + i;
+            m1[i] = col < g.ldp ? fold_grid(bound[col]) : 0.0;
+        }
+        __syncthreads();
+    }
+    for_rows<LPR, NV>(sc, ln, [&](int row) {
         AT acc[NV];
         XT xs[NV];
         bool self;
@@ -336,14 +390,15 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
                 if (!self) ldpair(X + (size_t)row * g.ldp + ln.c[v], xr);
                 const double2 p = wide(xr);
                 const double2 q = as_stored(acc[v], (const TX *)y);
-                dotacc[0][v].x = fma(p.x, q.x, dotacc[0][v].x);
-                dotacc[0][v].y = fma(p.y, q.y, dotacc[0][v].y);
+                const int cl = 2 * (ln.lr + LPR * v);
+                fold_add(p.x, q.x, m1[cl], f2, dotacc[0][v].x, dotacc[1][v].x);
+                fold_add(p.y, q.y, m1[cl + 1], f2, dotacc[0][v].y, dotacc[1][v].y);
             }
         }
-    }
+    });
     if (WITH_DOT) {
-        double *const parts[1] = {part};
-        block_partials<LPR, NV, 1>(g, ln, sc.cc, sc.prow, dotacc, parts);
+        double *const parts[2] = {part, part + (size_t)g.nrt * g.ldp};
+        block_partials<LPR, NV, 2>(g, ln, sc.cc, sc.prow, dotacc, parts);
     }
 }
 
@@ -352,26 +407,34 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(Geom g, const int32_t *__restric
 // delta = sum_i (D^-1 R)[i,c] W[i,c] (R of the own row comes from the gather
 // of the diagonal entry).  beta == nullptr: S = W.
 template <int LPR, int NV>
-__global__ __launch_bounds__(BLOCK) void k_spmm_sr(Geom g, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(spmm_waves<NV>())))
+void k_spmm_sr(Geom g, const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci,
                                                    const double *__restrict__ vs,
                                                    const double *__restrict__ dinv,
                                                    const double *__restrict__ R,
                                                    const double *__restrict__ beta,
-                                                   double *__restrict__ S, double *part) {
+                                                   double *__restrict__ S, double *part,
+                                                   const double *__restrict__ bound) {
     Sched sc;
     if (!block_sched<Lane<LPR, NV>::RSTEP>(g, sc)) return;
     Lane<LPR, NV> ln(g, sc.cc);
     double2 be[NV];
-    double2 dotacc[1][NV];
+    constexpr int CW = Lane<LPR, NV>::CW;
+    __shared__ double m1[CW];   // first fold grid of the chunk's columns
+    double2 dotacc[2][NV];      // the two fold sums
+    const double f2 = ldexp(1.0, g.cl2n - 52);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         be[v] = (ln.ok[v] && beta) ? ld2(beta + ln.c[v]) : make_double2(0.0, 0.0);
-        dotacc[0][v] = make_double2(0.0, 0.0);
+        dotacc[0][v] = dotacc[1][v] = make_double2(0.0, 0.0);
     }
-    for (int base = sc.rs + sc.first; base < sc.re; base += sc.stride) {
-        const int row = base + ln.slot;
-        if (row >= sc.re) continue;
+    for (int i = threadIdx.x; i < CW; i += BLOCK) {
+        const int col = sc.cc * CW + i;
+        m1[i] = col < g.ldp ? fold_grid(bound[col]) : 0.0;
+    }
+    __syncthreads();
+    for_rows<LPR, NV>(sc, ln, [&](int row) {
         // the row's S entries are requested before the gathers
         double2 so[NV];
 #pragma unroll
@@ -393,12 +456,13 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_sr(Geom g, const int32_t *__rest
             stn2(S + o, sn);
             double2 xr = xs[v];
             if (!self) xr = ld2(R + o);
-            dotacc[0][v].x = fma(xr.x * di, acc[v].x, dotacc[0][v].x);
-            dotacc[0][v].y = fma(xr.y * di, acc[v].y, dotacc[0][v].y);
+            const int cl = 2 * (ln.lr + LPR * v);
+            fold_add(xr.x * di, acc[v].x, m1[cl], f2, dotacc[0][v].x, dotacc[1][v].x);
+            fold_add(xr.y * di, acc[v].y, m1[cl + 1], f2, dotacc[0][v].y, dotacc[1][v].y);
         }
-    }
-    double *const parts[1] = {part};
-    block_partials<LPR, NV, 1>(g, ln, sc.cc, sc.prow, dotacc, parts);
+    });
+    double *const parts[2] = {part, part + (size_t)g.nrt * g.ldp};
+    block_partials<LPR, NV, 2>(g, ln, sc.cc, sc.prow, dotacc, parts);
 }
 
 // Rows per lane per step in the streaming kernels (measured best on gfx950:
@@ -726,6 +790,8 @@ __global__ __launch_bounds__(BLOCK) void k_residual(Geom g, const int32_t *__res
 struct Scal {
     double *rho, *alpha, *beta, *bb, *rr;
     double *tt;                       // per-column stop level for ||r||^2
+    double *bd;                       // per-column bound on sum |t| of the SpMM's dot
+    const double *kappa;              // max_i sum_j |a_ij| / d_i (device scalar)
     int32_t *iters, *active, *flag;   // flag[0]: breakdown
 };
 
@@ -750,6 +816,23 @@ __device__ __forceinline__ double col_sum(const double *part, int nrt, int c) {
     return r;
 }
 
+// A dot product of the SpMM from its two fold partials (exact sums).
+__device__ __forceinline__ double col_sum2(const double *part, int nrt, int ldp, int c) {
+    const double s1 = col_sum(part, nrt, c);
+    const double s2 = col_sum(part + (size_t)nrt * ldp, nrt, c);
+    return s1 + s2;
+}
+
+// Bounds of the SpMM's dot for the fold grids.  With z = D^-1 r and w = A z,
+// sum_i |z_i w_i| <= sum_ij |a_ij| |z_i| |z_j| <= sum_i z_i^2 sum_j |a_ij|
+// <= kappa gamma, gamma = r.D^-1 r: so 2 kappa gamma bounds the single-
+// reduction delta and the first p.Ap (p = z).  Later p.Ap of the classic
+// form take 2^16 times the previous one (no a-priori bound; an exceeded
+// bound only makes the sum depend on the grouping again).
+__device__ __forceinline__ double bound_z(const Scal &sc, double gamma) {
+    return 2.0 * sc.kappa[0] * gamma;
+}
+
 // tt = max(tol^2 ||b||^2, eta^2 ||r||^2): eta = 0 runs to the tolerance; the
 // mixed-precision mode uses eta > 0 so that each float32 cycle only reduces
 // its starting residual by eta before the FP64 refinement step.
@@ -764,6 +847,7 @@ __global__ __launch_bounds__(RED) void k_red_init(Scal sc, const double *pbb, co
         sc.bb[c] = bb;
         sc.rho[c] = rz;
         sc.rr[c] = rr;
+        sc.bd[c] = bound_z(sc, rz);
         sc.tt[c] = fmax(tol2 * bb, eta2 * rr);
         sc.iters[c] = 0;
         sc.alpha[c] = 0.0;
@@ -773,14 +857,15 @@ __global__ __launch_bounds__(RED) void k_red_init(Scal sc, const double *pbb, co
 }
 
 __global__ __launch_bounds__(RED) void k_red_alpha(Scal sc, double *alpha, const double *ppq,
-                                                   int nrt) {
+                                                   int nrt, int ldp) {
     const int c = blockIdx.x;
-    const double pq = col_sum(ppq, nrt, c);
+    const double pq = col_sum2(ppq, nrt, ldp, c);
     if (threadIdx.x == 0) {
         double a = 0.0;
         if (sc.active[c]) {
             if (pq > 0.0) {
                 a = sc.rho[c] / pq;
+                sc.bd[c] = 65536.0 * pq;
             } else {
                 sc.active[c] = 0;
                 sc.flag[0] = 1;
@@ -795,9 +880,9 @@ __global__ __launch_bounds__(RED) void k_red_alpha(Scal sc, double *alpha, const
 // alpha = gamma / (delta - beta gamma / alpha_prev) (= gamma / delta when
 // beta = 0).  sc.alpha keeps alpha_prev.
 __global__ __launch_bounds__(RED) void k_red_alpha_sr(Scal sc, double *alpha, const double *pdelta,
-                                                      int nrt) {
+                                                      int nrt, int ldp) {
     const int c = blockIdx.x;
-    const double delta = col_sum(pdelta, nrt, c);
+    const double delta = col_sum2(pdelta, nrt, ldp, c);
     if (threadIdx.x == 0) {
         double a = 0.0;
         if (sc.active[c]) {
@@ -818,7 +903,7 @@ __global__ __launch_bounds__(RED) void k_red_alpha_sr(Scal sc, double *alpha, co
 // beta = rz / rho of the new residual; bslot (optional) keeps a copy in the
 // ring of step coefficients.
 __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, const double *prr,
-                                                  int nrt, double *bslot) {
+                                                  int nrt, double *bslot, int sr) {
     const int c = blockIdx.x;
     const double rz = col_sum(prz, nrt, c);
     const double rr = col_sum(prr, nrt, c);
@@ -832,6 +917,7 @@ __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, co
             } else {
                 b = rz / sc.rho[c];
                 sc.rho[c] = rz;
+                if (sr) sc.bd[c] = bound_z(sc, rz);
             }
         }
         sc.beta[c] = b;
@@ -853,6 +939,7 @@ __global__ __launch_bounds__(RED) void k_red_refine(Scal sc, const double *prz,
         sc.rr[c] = rr;
         if (again) {
             sc.rho[c] = rz;
+            sc.bd[c] = bound_z(sc, rz);
             sc.tt[c] = fmax(tol2 * sc.bb[c], eta2 * rr);
         }
         sc.alpha[c] = 0.0;
@@ -864,6 +951,42 @@ __global__ __launch_bounds__(RED) void k_red_sum(const double *part, int nrt, do
     const int c = blockIdx.x;
     const double s = col_sum(part, nrt, c);
     if (threadIdx.x == 0) out[c] = s;
+}
+
+// kappa = max over solver rows of sum_j |a_ij| / d_i (a maximum: the same in
+// any order).  Partial maxima per block, then one block.
+constexpr int KAPPA_BLOCKS = 256;
+__global__ __launch_bounds__(RED) void k_kappa_part(const int32_t *rp, const double *va,
+                                                    const double *dinv, int32_t n,
+                                                    double *part) {
+    __shared__ double s[RED];
+    double m = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * RED + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * RED) {
+        double a = 0.0;
+        for (int32_t k = rp[r]; k < rp[r + 1]; ++k) a += fabs(va[k]);
+        m = fmax(m, a * dinv[r]);
+    }
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = RED / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(RED) void k_kappa_final(const double *part, int np, double *kappa) {
+    __shared__ double s[RED];
+    double m = 0.0;
+    for (int k = threadIdx.x; k < np; k += RED) m = fmax(m, part[k]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = RED / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) kappa[0] = s[0] > 0.0 ? s[0] : 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -886,6 +1009,7 @@ constexpr TileCfg kTiles[] = {
     {8, 1, 1, "lpr8_nv1_cw16_front"},    {8, 2, 1, "lpr8_nv2_cw32_front"},
 };
 constexpr int NTILES = sizeof(kTiles) / sizeof(kTiles[0]);
+static_assert(NTILES <= 32, "residency cache size");
 
 #define ZI_TILE_SWITCH(tile, FN, ...)                       \
     switch (kTiles[tile].lpr * 8 + kTiles[tile].nv) {       \
@@ -921,13 +1045,20 @@ int auto_tile(int ldp) {
     return best >= 0 ? best : 9;      // wider than any front tile: lpr64_nv4_cw512
 }
 
-Geom make_geom(int n, int ldp, int tile) {
+// resident: blocks of the kernel that one XCD holds at once (0: no cap).  In
+// the cooperative front every block of a unit must be resident: a block
+// walks its unit's whole row range, so blocks that only start when earlier
+// ones have finished would sweep the range a second time, behind the first
+// front, and fetch every shared neighbour row again.
+Geom make_geom(int n, int ldp, int tile, int resident = 0) {
     const TileCfg &t = kTiles[tile];
     const int cw = 2 * t.lpr * t.nv;
     const int rstep = WAVES * (64 / t.lpr);
     Geom g{};
     g.n = n;
     g.ldp = ldp;
+    g.cl2n = 1;
+    while ((1ll << g.cl2n) < (long long)n) ++g.cl2n;
     g.ncc = (ldp + cw - 1) / cw;
     g.front = t.front;
     if (!t.front) {
@@ -946,6 +1077,7 @@ Geom make_geom(int n, int ldp, int tile) {
         g.U = g.ncc * g.P;                         // units (chunk, part)
         const int groups = (n + g.P - 1) / g.P / rstep + 1;   // row groups per unit
         int B = TARGET_BLOCKS / g.U;
+        if (resident > 0) B = std::min(B, resident / ((g.U + 7) / 8));
         if (B < 1) B = 1;
         if (B > groups) B = groups;
         g.B = B;
@@ -956,15 +1088,55 @@ Geom make_geom(int n, int ldp, int tile) {
     return g;
 }
 
+// Blocks of BLOCK threads that one XCD (a eighth of the CUs) holds at once
+// for a kernel, from its register and LDS use.
+int cus_per_xcd() {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cu < 8)
+        return 1;
+    return cu / 8;
+}
+
+template <class K>
+int resident_per_xcd(K kern) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, BLOCK, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    return nb * cus_per_xcd();
+}
+
+// Kernels whose front geometry is capped by their own residency.
+enum class GK { SPMM_SR, SPMM_DOT64, SPMM_DOT32, SPMM64, SPMM32F, UPDATE64, UPDATE32,
+                PUPDATE64, PUPDATE32, RESIDUAL64, RESIDUAL32, COUNT };
+
+template <int LPR, int NV>
+void occupancy_of(GK k, int *out);
+
+int resident_blocks(GK k, int tile) {
+    static std::mutex mu;
+    static int cache[(int)GK::COUNT][32] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    int &r = cache[(int)k][tile];
+    if (r == 0) ZI_TILE_SWITCH(tile, occupancy_of, k, &r);
+    return r;
+}
+
+Geom make_geom_for(GK k, int n, int ldp, int tile) {
+    return make_geom(n, ldp, tile, resident_blocks(k, tile));
+}
+
 template <int LPR, int NV, class TV, class TX>
 void launch_spmm(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t *ci,
-                 const TV *va, const TX *X, TX *Y, double *part) {
+                 const TV *va, const TX *X, TX *Y, double *part,
+                 const double *bound = nullptr) {
     if (part)
         hipLaunchKernelGGL((k_spmm<LPR, NV, TV, TX, true>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g,
-                           rp, ci, va, X, Y, part);
+                           rp, ci, va, X, Y, part, bound);
     else
         hipLaunchKernelGGL((k_spmm<LPR, NV, TV, TX, false>), dim3(g.nb_pad), dim3(BLOCK), 0, s,
-                           g, rp, ci, va, X, Y, part);
+                           g, rp, ci, va, X, Y, part, bound);
 }
 
 template <int LPR, int NV, class TP>
@@ -977,15 +1149,39 @@ void launch_update(const Geom &g, hipStream_t s, const double *alpha, const doub
 template <int LPR, int NV>
 void launch_spmm_sr(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t *ci,
                     const double *vs, const double *dinv, const double *R, const double *beta,
-                    double *S, double *part) {
+                    double *S, double *part, const double *bound) {
     hipLaunchKernelGGL((k_spmm_sr<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, rp, ci, vs,
-                       dinv, R, beta, S, part);
+                       dinv, R, beta, S, part, bound);
+}
+
+template <int LPR, int NV>
+void occupancy_of(GK k, int *out) {
+    switch (k) {
+        case GK::SPMM_SR: *out = resident_per_xcd(k_spmm_sr<LPR, NV>); break;
+        case GK::SPMM_DOT64:
+            *out = resident_per_xcd(k_spmm<LPR, NV, double, double, true>);
+            break;
+        case GK::SPMM_DOT32:
+            *out = resident_per_xcd(k_spmm<LPR, NV, double, float, true>);
+            break;
+        case GK::SPMM64: *out = resident_per_xcd(k_spmm<LPR, NV, double, double, false>); break;
+        case GK::SPMM32F: *out = resident_per_xcd(k_spmm<LPR, NV, float, float, false>); break;
+        case GK::UPDATE64: *out = resident_per_xcd(k_update<LPR, NV, double>); break;
+        case GK::UPDATE32: *out = resident_per_xcd(k_update<LPR, NV, float>); break;
+        case GK::PUPDATE64: *out = resident_per_xcd(k_pupdate<LPR, NV, double>); break;
+        case GK::PUPDATE32: *out = resident_per_xcd(k_pupdate<LPR, NV, float>); break;
+        case GK::RESIDUAL64: *out = resident_per_xcd(k_residual<LPR, NV, double>); break;
+        default: *out = resident_per_xcd(k_residual<LPR, NV, float>); break;
+    }
 }
 
 // The flush writes no partial sums, so it runs with its own geometry: the
 // cooperative front of 32 lanes x 2 pairs per row (128-column chunks), the
 // fastest for it on the 2 mm sphere, whatever tile the SpMM uses.
 constexpr int FLUSH_TILE = 13;   // lpr32_nv2_cw128_front
+// Residual update, direction update and residual b - A x: the same fixed
+// geometry (32 lanes x 2 pairs per row, 128-column front chunks).
+constexpr int STREAM_TILE = FLUSH_TILE;
 static_assert(kTiles[FLUSH_TILE].lpr == 32 && kTiles[FLUSH_TILE].nv == 2 &&
                   kTiles[FLUSH_TILE].front == 1,
               "flush geometry");
@@ -993,14 +1189,16 @@ static_assert(kTiles[FLUSH_TILE].lpr == 32 && kTiles[FLUSH_TILE].nv == 2 &&
 template <class TP>
 void launch_xflush(int n, int ldp, hipStream_t s, int cnt, const double *alphas, Ring<TP> ring,
                    double *X) {
-    const Geom g = make_geom(n, ldp, FLUSH_TILE);
+    static const int res = resident_per_xcd(k_xflush<TP>);
+    const Geom g = make_geom(n, ldp, FLUSH_TILE, res);
     hipLaunchKernelGGL((k_xflush<TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas, ring,
                        X);
 }
 
 void launch_pflush(int n, int ldp, hipStream_t s, int cnt, const double *alphas,
                    const double *betas, Ring<double> ring, const double *dinv, double *P, double *X) {
-    const Geom g = make_geom(n, ldp, FLUSH_TILE);
+    static const int res = resident_per_xcd(k_pflush<32, 2>);
+    const Geom g = make_geom(n, ldp, FLUSH_TILE, res);
     hipLaunchKernelGGL((k_pflush<32, 2>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
                        betas, ring, dinv, P, X);
 }
@@ -1053,8 +1251,9 @@ struct zi_solver_ws {
     double *bring = nullptr;                                  // LAZY x ldp betas (single-reduction)
     double *bflush = nullptr;                                 // LAZY x ldp scratch
     double *vs = nullptr;                                     // values of A D^-1
-    double *part[3] = {nullptr, nullptr, nullptr};
-    double *sc_d = nullptr;     // rho alpha beta bb rr tt (6 ldp)
+    double *part[3] = {nullptr, nullptr, nullptr};   // 2 x nrt x ldp each (two folds)
+    double *kap = nullptr;      // kappa and its block partial maxima
+    double *sc_d = nullptr;     // rho alpha beta bb rr tt bd (7 ldp)
     int32_t *sc_i = nullptr;    // iters active (2 ldp) + flag
     std::vector<hipEvent_t> ev;
     zi::Pool pool;
@@ -1099,13 +1298,14 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
         (st = ws->pool.alloc(&ws->vs, (size_t)std::max<int64_t>(sys->sp_nnz, 1))) != ZI_OK ||
         (st = ws->pool.alloc(&ws->Q, blk)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->dinv, (size_t)sys->n)) != ZI_OK ||
-        (st = ws->pool.alloc(&ws->sc_d, (size_t)6 * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->sc_d, (size_t)7 * ldp)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->kap, (size_t)KAPPA_BLOCKS + 1)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->sc_i, (size_t)2 * ldp + 1)) != ZI_OK) {
         delete ws;
         return st;
     }
     for (int q = 0; q < 3; ++q) {
-        if ((st = ws->pool.alloc(&ws->part[q], (size_t)nrt_max * ldp)) != ZI_OK) {
+        if ((st = ws->pool.alloc(&ws->part[q], (size_t)2 * nrt_max * ldp)) != ZI_OK) {
             delete ws;
             return st;
         }
@@ -1155,7 +1355,12 @@ namespace {
 struct SolveCtx {
     zi_system *sys = nullptr;
     zi_solver_ws *ws = nullptr;
-    Geom g{};
+    Geom g{};                 // SpMM (the tile); partials of red_alpha
+    // The streaming kernels run with one fixed geometry whatever the tile, so
+    // their partial sums (and all results) do not depend on the tile.
+    Geom gu{};                // residual update; partials of red_beta
+    Geom gp{};                // direction update (classic form)
+    Geom gr{};                // residual b - A x; partials of red_init, red_refine
     int tile = 0, ldp = 0, L = 0, maxit = 0, check = 0;
     double tol = 0, tol2 = 0;
     double eta2 = 0;          // inner-cycle reduction (squared); 0 = run to tol
@@ -1287,25 +1492,28 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
         Timed t(c, 0, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
         ZI_TILE_SWITCH(tile, launch_spmm, g, s, c.sys->sp_ptr, c.sys->sp_col, va, (const TP *)Pk,
-                       Q, ws->part[0]);
+                       Q, ws->part[0], (const double *)c.sc.bd);
     }
-    hipLaunchKernelGGL(k_red_alpha, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt);
+    hipLaunchKernelGGL(k_red_alpha, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt,
+                       c.ldp);
     {
         Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
-        ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)al, (const double *)ws->dinv,
-                       (const TP *)ws->R, (const TP *)Q, reinterpret_cast<TP *>(ws->R),
-                       ws->part[1], ws->part[2]);
+        launch_update<32, 2, TP>(c.gu, s, (const double *)al, (const double *)ws->dinv,
+                                 (const TP *)ws->R, (const TP *)Q, reinterpret_cast<TP *>(ws->R),
+                                 ws->part[1], ws->part[2]);
     }
     if ((k + 1) % LAZY == 0 || replace_r) ZI_TRY(enqueue_flush<TP>(c, k + 1, s));
+    // a reliable update rewrites the partials of part[0..2] with c.gr's layout
+    const int nrt_beta = replace_r ? c.gr.nrt : c.gu.nrt;
     if (replace_r) ZI_TRY(true_residual(c, s, true));
     hipLaunchKernelGGL(k_red_beta, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[1], ws->part[2],
-                       g.nrt, (double *)nullptr);
+                       nrt_beta, (double *)nullptr, 0);
     {
         Timed t(c, 2, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
-        ZI_TILE_SWITCH(tile, launch_pupdate, g, s, (const double *)c.sc.beta,
-                       (const double *)ws->dinv, (const TP *)ws->R, (const TP *)Pk, Pn);
+        launch_pupdate<32, 2, TP>(c.gp, s, (const double *)c.sc.beta, (const double *)ws->dinv,
+                                  (const TP *)ws->R, (const TP *)Pk, Pn);
     }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
@@ -1357,19 +1565,21 @@ zi_status enqueue_iteration_sr(SolveCtx &c, int k, hipStream_t s) {
         ZI_TRY(t.st);
         ZI_TILE_SWITCH(tile, launch_spmm_sr, g, s, c.sys->sp_ptr, c.sys->sp_col,
                        (const double *)ws->vs, (const double *)ws->dinv,
-                       (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q, ws->part[0]);
+                       (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q, ws->part[0],
+                       (const double *)c.sc.bd);
     }
-    hipLaunchKernelGGL(k_red_alpha_sr, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt);
+    hipLaunchKernelGGL(k_red_alpha_sr, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt,
+                       c.ldp);
     if ((k + 1) % LAZY == 0) ZI_TRY(enqueue_flush_sr(c, k + 1, s));
     {
         Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
-        ZI_TILE_SWITCH(tile, launch_update, g, s, (const double *)al, (const double *)ws->dinv,
-                       (const double *)c.Rsr(k), (const double *)ws->Q, c.Rsr(k + 1),
-                       ws->part[1], ws->part[2]);
+        launch_update<32, 2, double>(c.gu, s, (const double *)al, (const double *)ws->dinv,
+                                     (const double *)c.Rsr(k), (const double *)ws->Q,
+                                     c.Rsr(k + 1), ws->part[1], ws->part[2]);
     }
     hipLaunchKernelGGL(k_red_beta, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[1], ws->part[2],
-                       g.nrt, c.beta_slot(k + 1));
+                       c.gu.nrt, c.beta_slot(k + 1), 1);
     ZI_HIP(hipGetLastError());
     return ZI_OK;
 }
@@ -1404,13 +1614,13 @@ zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r) {
     ZI_TILE_SWITCH(c.tile, launch_spmm, c.g, s, c.sys->sp_ptr, c.sys->sp_col,
                    (const double *)c.sys->sp_val, (const double *)ws->X, ws->Q, (double *)nullptr);
     if (c.mixed) {   // R holds float32 in the mixed mode
-        ZI_TILE_SWITCH(c.tile, launch_residual, c.g, s, c.sys, (const int32_t *)c.colmap,
-                       ws->dinv, ws->Q, write_r ? reinterpret_cast<float *>(ws->R) : nullptr,
-                       ws->part[0], ws->part[1], ws->part[2]);
+        launch_residual<32, 2, float>(c.gr, s, c.sys, (const int32_t *)c.colmap, ws->dinv, ws->Q,
+                                      write_r ? reinterpret_cast<float *>(ws->R) : nullptr,
+                                      ws->part[0], ws->part[1], ws->part[2]);
     } else {
-        ZI_TILE_SWITCH(c.tile, launch_residual, c.g, s, c.sys, (const int32_t *)c.colmap,
-                       ws->dinv, ws->Q, write_r ? ws->R : nullptr, ws->part[0], ws->part[1],
-                       ws->part[2]);
+        launch_residual<32, 2, double>(c.gr, s, c.sys, (const int32_t *)c.colmap, ws->dinv,
+                                       ws->Q, write_r ? ws->R : nullptr, ws->part[0],
+                                       ws->part[1], ws->part[2]);
     }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
@@ -1420,12 +1630,13 @@ zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r) {
 zi_status enqueue_restart_direction(SolveCtx &c, hipStream_t s) {
     if (c.mixed) {
         float *p = c.P<float>(c.it);
-        ZI_TILE_SWITCH(c.tile, launch_pupdate, c.g, s, (const double *)nullptr,
-                       (const double *)c.ws->dinv, (const float *)c.ws->R, (const float *)p, p);
+        launch_pupdate<32, 2, float>(c.gp, s, (const double *)nullptr, (const double *)c.ws->dinv,
+                                     (const float *)c.ws->R, (const float *)p, p);
     } else {
         double *p = c.P<double>(c.it);
-        ZI_TILE_SWITCH(c.tile, launch_pupdate, c.g, s, (const double *)nullptr,
-                       (const double *)c.ws->dinv, (const double *)c.ws->R, (const double *)p, p);
+        launch_pupdate<32, 2, double>(c.gp, s, (const double *)nullptr,
+                                      (const double *)c.ws->dinv, (const double *)c.ws->R,
+                                      (const double *)p, p);
     }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
@@ -1494,7 +1705,11 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     zi_solver_ws *ws = sys->ws;
     c.sys = sys;
     c.ws = ws;
-    c.g = make_geom(n, ldp, tile);
+    c.g = make_geom_for(c.sr ? GK::SPMM_SR : c.mixed ? GK::SPMM_DOT32 : GK::SPMM_DOT64, n, ldp,
+                        tile);
+    c.gu = make_geom_for(c.mixed ? GK::UPDATE32 : GK::UPDATE64, n, ldp, STREAM_TILE);
+    c.gp = make_geom_for(c.mixed ? GK::PUPDATE32 : GK::PUPDATE64, n, ldp, STREAM_TILE);
+    c.gr = make_geom_for(c.mixed ? GK::RESIDUAL32 : GK::RESIDUAL64, n, ldp, STREAM_TILE);
     c.tile = tile;
     c.ldp = ldp;
     c.L = L;
@@ -1525,6 +1740,8 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     sc.bb = ws->sc_d + 3 * ldp;
     sc.rr = ws->sc_d + 4 * ldp;
     sc.tt = ws->sc_d + 5 * ldp;
+    sc.bd = ws->sc_d + 6 * ldp;
+    sc.kappa = ws->kap;
     sc.iters = ws->sc_i;
     sc.active = ws->sc_i + ldp;
     sc.flag = ws->sc_i + 2 * ldp;
@@ -1532,6 +1749,11 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     hipLaunchKernelGGL(k_dinv, dim3((n + 255) / 256), dim3(256), 0, s,
                        o->precond == ZI_PREC_LDP ? sys->absrow : sys->diag, sys->perm, n,
                        ws->dinv);
+    hipLaunchKernelGGL(k_kappa_part, dim3(KAPPA_BLOCKS), dim3(RED), 0, s,
+                       (const int32_t *)sys->sp_ptr, (const double *)sys->sp_val,
+                       (const double *)ws->dinv, n, ws->kap + 1);
+    hipLaunchKernelGGL(k_kappa_final, dim3(1), dim3(RED), 0, s, (const double *)(ws->kap + 1),
+                       KAPPA_BLOCKS, ws->kap);
     ZI_TRY(fill_i32(sc.flag, 0, 1, s));
     ZI_TRY(fill_f64(ws->X, 0.0, (size_t)n * ldp, s));
     if (o->x0) {
@@ -1539,17 +1761,18 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
         ZI_TRY(true_residual(c, s, true));
     } else {
         if (c.mixed) {
-            ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, (const int32_t *)c.colmap,
-                           ws->dinv, (const double *)nullptr, reinterpret_cast<float *>(ws->R),
-                           ws->part[0], ws->part[1], ws->part[2]);
+            launch_residual<32, 2, float>(c.gr, s, sys, (const int32_t *)c.colmap, ws->dinv,
+                                          (const double *)nullptr,
+                                          reinterpret_cast<float *>(ws->R), ws->part[0],
+                                          ws->part[1], ws->part[2]);
         } else {
-            ZI_TILE_SWITCH(tile, launch_residual, c.g, s, sys, (const int32_t *)c.colmap,
-                           ws->dinv, (const double *)nullptr, ws->R, ws->part[0], ws->part[1],
-                           ws->part[2]);
+            launch_residual<32, 2, double>(c.gr, s, sys, (const int32_t *)c.colmap, ws->dinv,
+                                           (const double *)nullptr, ws->R, ws->part[0],
+                                           ws->part[1], ws->part[2]);
         }
     }
     hipLaunchKernelGGL(k_red_init, dim3(ldp), dim3(RED), 0, s, sc, ws->part[0], ws->part[1],
-                       ws->part[2], c.g.nrt, L, c.tol2, c.eta2);
+                       ws->part[2], c.gr.nrt, L, c.tol2, c.eta2);
     if (c.sr) {
         // A D^-1, and zero S, lazy P and beta_0 (beta_0 = 0 multiplies them)
         const int64_t nnz = sys->sp_nnz;
@@ -1579,7 +1802,7 @@ zi_status solve_after_converged(SolveCtx &c, hipStream_t s) {
     ZI_TRY(flush_all(c, s));
     ZI_TRY(true_residual(c, s, true));
     hipLaunchKernelGGL(k_red_refine, dim3(c.ldp), dim3(RED), 0, s, c.sc, c.ws->part[1],
-                       c.ws->part[2], c.g.nrt, c.L, c.tol2, c.eta2);
+                       c.ws->part[2], c.gr.nrt, c.L, c.tol2, c.eta2);
     ZI_HIP(hipGetLastError());
     ZI_TRY(read_active(c, s));
     if (!c.any_active) {
@@ -1620,7 +1843,7 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
     ZI_HIP(hipMemcpyAsync(h_bb.data(), c.sc.bb, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
     if (st && st->relres_true) {
         ZI_TRY(true_residual(c, s, false));
-        hipLaunchKernelGGL(k_red_sum, dim3(ldp), dim3(RED), 0, s, ws->part[2], c.g.nrt,
+        hipLaunchKernelGGL(k_red_sum, dim3(ldp), dim3(RED), 0, s, ws->part[2], c.gr.nrt,
                            c.sc.alpha);   // alpha reused as scratch
         ZI_HIP(hipGetLastError());
         ZI_HIP(hipMemcpyAsync(h_true.data(), c.sc.alpha, sizeof(double) * ldp,
@@ -1944,13 +2167,14 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     ZI_HIP(hipEventCreate(&e1));
     int bt = 0;
     double bms = 1e30;
-    // Each tile is scored by one iteration's kernels: the SpMM, the residual
-    // update and the direction update (classic form), each the best of three
-    // launches after a warm-up (the X flushes run with their own geometry).
+    // Each tile is scored by the iteration's SpMM, the best of three launches
+    // after a warm-up: the other kernels of an iteration run with one fixed
+    // geometry whatever the tile.
+    const bool f32 = precision == ZI_FP32_SPMM_IR;
     for (int t = 0; t < NTILES; ++t) {
-        const Geom g = make_geom(n, ldp, t);
+        const Geom gs = make_geom_for(f32 ? GK::SPMM_DOT32 : GK::SPMM_SR, n, ldp, t);
         double total = 0.0;
-        const int kinds = precision == ZI_FP32_SPMM_IR ? 3 : 2;
+        const int kinds = 1;
         for (int kind = 0; kind < kinds; ++kind) {
             double tmin = 1e30;
             for (int rep = 0; rep < 4; ++rep) {
@@ -1960,31 +2184,17 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                     float *P1 = reinterpret_cast<float *>(ws->P[1]);
                     float *Qf = reinterpret_cast<float *>(ws->Q);
                     float *Rf = reinterpret_cast<float *>(ws->R);
-                    if (kind == 0) {
-                        ZI_TILE_SWITCH(t, launch_spmm, g, s, sys->sp_ptr, sys->sp_col,
-                                       (const double *)sys->sp_val, (const float *)P0, Qf,
-                                       ws->part[0]);
-                    } else if (kind == 1) {
-                        ZI_TILE_SWITCH(t, launch_update, g, s, (const double *)ws->aring,
-                                       (const double *)ws->dinv, (const float *)Rf,
-                                       (const float *)Qf, Rf, ws->part[1], ws->part[2]);
-                    } else {
-                        ZI_TILE_SWITCH(t, launch_pupdate, g, s, (const double *)ws->bring,
-                                       (const double *)ws->dinv, (const float *)Rf,
-                                       (const float *)P0, P1);
-                    }
+                    (void)kind;
+                    (void)P1;
+                    (void)Rf;
+                    ZI_TILE_SWITCH(t, launch_spmm, gs, s, sys->sp_ptr, sys->sp_col,
+                                   (const double *)sys->sp_val, (const float *)P0, Qf,
+                                   ws->part[0], (const double *)ws->aring);
                 } else {   // the FP64 solve's default (single-reduction) kernels
-                    if (kind == 0) {
-                        ZI_TILE_SWITCH(t, launch_spmm_sr, g, s, sys->sp_ptr, sys->sp_col,
-                                       (const double *)sys->sp_val, (const double *)ws->dinv,
-                                       (const double *)ws->P[0], (const double *)ws->bring,
-                                       ws->Q, ws->part[0]);
-                    } else {
-                        ZI_TILE_SWITCH(t, launch_update, g, s, (const double *)ws->aring,
-                                       (const double *)ws->dinv, (const double *)ws->P[0],
-                                       (const double *)ws->Q, ws->P[1], ws->part[1],
-                                       ws->part[2]);
-                    }
+                    ZI_TILE_SWITCH(t, launch_spmm_sr, gs, s, sys->sp_ptr, sys->sp_col,
+                                   (const double *)sys->sp_val, (const double *)ws->dinv,
+                                   (const double *)ws->P[0], (const double *)ws->bring, ws->Q,
+                                   ws->part[0], (const double *)ws->aring);
                 }
                 ZI_HIP(hipGetLastError());
                 ZI_HIP(hipEventRecord(e1, s));
@@ -2021,7 +2231,7 @@ zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double 
         return ZI_EINVAL;
     }
     const int n = sys->n;
-    const Geom g = make_geom(n, k, tile);
+    const Geom g = make_geom_for(GK::SPMM64, n, k, tile);
     Pool tmp;   // the blocks in solver row order
     double *Xp = nullptr, *Yp = nullptr;
     ZI_TRY(tmp.alloc(&Xp, (size_t)n * k));
@@ -2052,7 +2262,7 @@ namespace zi {
 zi_status spmm_f32(const int32_t *rp, const int32_t *ci, const float *va, const float *X, float *Y,
                    int32_t n, int32_t ld, hipStream_t s) {
     const int tile = auto_tile(ld);
-    const Geom g = make_geom(n, ld, tile);
+    const Geom g = make_geom_for(GK::SPMM32F, n, ld, tile);
     ZI_TILE_SWITCH(tile, launch_spmm, g, s, rp, ci, va, X, Y, (double *)nullptr);
     ZI_HIP(hipGetLastError());
     return ZI_OK;
