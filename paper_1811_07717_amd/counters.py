@@ -46,20 +46,26 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def per_kernel(path):
-    """Mean counter value (KiB) and launch count per solver kernel key."""
+def per_kernel(path, spmm_args=None):
+    """Mean counter value (KiB) and launch count per solver kernel key.
+    spmm_args ("16, 2"): count only SpMM launches of that tile (the run's
+    tuned tile; the autotuner's launches of other tiles are left out)."""
     vals = collections.defaultdict(list)
     with open(path) as f:
         for r in csv.DictReader(f):
+            name = r["Kernel_Name"]
             for pat, key in KERNELS:
-                if pat.search(r["Kernel_Name"]):
+                if pat.search(name):
+                    if (spmm_args and key.startswith("spmm")
+                            and f"<{spmm_args}" not in name):
+                        break
                     vals[key].append(float(r["Counter_Value"]))
                     break
     return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
 
 
-def summarize(fetch_csv, write_csv, copy_mib):
-    fe, wr = per_kernel(fetch_csv), per_kernel(write_csv)
+def summarize(fetch_csv, write_csv, copy_mib, spmm_args=None):
+    fe, wr = per_kernel(fetch_csv, spmm_args), per_kernel(write_csv, spmm_args)
     if "copy" not in fe or "copy" not in wr:
         raise SystemExit("no k_copy2 launch in the counter files (run bench.py --calib-copy-mb)")
     true_kib = copy_mib * 1024.0
@@ -87,12 +93,17 @@ def main():
     p.add_argument("--md", help="write a markdown table here")
     p.add_argument("--command", default="", help="command line to record in the table")
     a = p.parse_args()
-    res, ff, wf = summarize(a.fetch, a.write, a.copy_mib)
-    alg = {}
+    alg, spmm_args = {}, None
     if a.bench:
         with open(a.bench) as f:
             line = [ln for ln in f.read().splitlines() if ln.startswith("{")][-1]
-        alg = {k: v["bytes_per_launch"] for k, v in json.loads(line)["solver_kernels"].items()}
+        b = json.loads(line)
+        alg = {k: v["bytes_per_launch"] for k, v in b["solver_kernels"].items()}
+        tuned = (b.get("autotune") or {}).get("tile")
+        m = re.match(r"lpr(\d+)_nv(\d+)_", tuned or "")
+        if m:
+            spmm_args = f"{m.group(1)}, {m.group(2)}"
+    res, ff, wf = summarize(a.fetch, a.write, a.copy_mib, spmm_args)
     h = source_hash()
     if a.update:
         d = {}
