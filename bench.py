@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--precond", default="jacobi")
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32_spmm_ir"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-batch", dest="batch", action="store_false",
+                   help="skip the batched-heads measurement (64 uneven heads, one after the "
+                        "other and in one zi_transfer_solve_batch call)")
     p.add_argument("--mixed", action="store_true",
                    help="also time the same builds with the mixed-precision solve (fp32 "
                         "search directions and products, fp64 recurrences)")
@@ -421,6 +424,12 @@ def main():
         out["autotune"] = tuned
     if smp is not None:
         out["cpu_baseline"] = cpu_baseline(smp, H, int(s0.nnz), iters, K)
+    if a.batch:
+        T = LF = None   # the 1 mm blocks go back before the heads are built
+        torch.cuda.empty_cache()
+        zi.release_cached_memory()
+        import bench_batch
+        out["batched_heads"] = bench_batch.measure(64, "fp64", log=log)
     if mixed is not None:
         out["mixed_precision"] = mixed
     print(json.dumps(out))

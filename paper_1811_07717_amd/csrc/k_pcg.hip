@@ -44,6 +44,10 @@ struct Geom {
     int nrt;              // partial-sum rows per column
     int nb, nb_pad;       // blocks (nb_pad: launched, a multiple of 8)
     int cl2n;             // ceil(log2 n): terms per column of a dot product
+    int slabs;            // front schedule: launches per product, each over a slab of every
+    int slab;             // row part (slab rows); the unit's blocks start each slab together
+    int cur;              // the slab this launch covers
+    const int32_t *gate;  // batched heads: 0 = the head has converged, launch does nothing
 };
 
 // Rows a block visits: base = rs + first + j * stride (base < re); the block's
@@ -62,6 +66,7 @@ struct Sched {
 //    close in time on the same XCD and their reuse stays in its L2.
 template <int RSTEP>
 __device__ __forceinline__ bool block_sched(const Geom &g, Sched &sc) {
+    if (g.gate && *g.gate == 0) return false;   // the whole grid of a converged head
     const int b = blockIdx.x;
     if (!g.front) {
         const int per = g.nb_pad >> 3;
@@ -83,11 +88,12 @@ __device__ __forceinline__ bool block_sched(const Geom &g, Sched &sc) {
     sc.cc = u / g.P;
     const int pr = u - sc.cc * g.P;
     const int part = (g.n + g.P - 1) / g.P;
-    sc.rs = pr * part;
-    sc.re = min(g.n, sc.rs + part);
+    const int pe = min(g.n, (pr + 1) * part);
+    sc.rs = min(pe, pr * part + g.cur * g.slab);
+    sc.re = min(pe, sc.rs + g.slab);
     sc.first = k * RSTEP;
     sc.stride = g.B * RSTEP;
-    sc.prow = pr * g.B + k;
+    sc.prow = (g.cur * g.P + pr) * g.B + k;
     return true;
 }
 
@@ -793,6 +799,7 @@ struct Scal {
     double *bd;                       // per-column bound on sum |t| of the SpMM's dot
     const double *kappa;              // max_i sum_j |a_ij| / d_i (device scalar)
     int32_t *iters, *active, *flag;   // flag[0]: breakdown
+    const int32_t *gate;              // as Geom::gate
 };
 
 constexpr int RED = 256;
@@ -859,6 +866,7 @@ __global__ __launch_bounds__(RED) void k_red_init(Scal sc, const double *pbb, co
 __global__ __launch_bounds__(RED) void k_red_alpha(Scal sc, double *alpha, const double *ppq,
                                                    int nrt, int ldp) {
     const int c = blockIdx.x;
+    if (sc.gate && *sc.gate == 0) return;
     const double pq = col_sum2(ppq, nrt, ldp, c);
     if (threadIdx.x == 0) {
         double a = 0.0;
@@ -882,6 +890,7 @@ __global__ __launch_bounds__(RED) void k_red_alpha(Scal sc, double *alpha, const
 __global__ __launch_bounds__(RED) void k_red_alpha_sr(Scal sc, double *alpha, const double *pdelta,
                                                       int nrt, int ldp) {
     const int c = blockIdx.x;
+    if (sc.gate && *sc.gate == 0) return;
     const double delta = col_sum2(pdelta, nrt, ldp, c);
     if (threadIdx.x == 0) {
         double a = 0.0;
@@ -905,6 +914,7 @@ __global__ __launch_bounds__(RED) void k_red_alpha_sr(Scal sc, double *alpha, co
 __global__ __launch_bounds__(RED) void k_red_beta(Scal sc, const double *prz, const double *prr,
                                                   int nrt, double *bslot, int sr) {
     const int c = blockIdx.x;
+    if (sc.gate && *sc.gate == 0) return;
     const double rz = col_sum(prz, nrt, c);
     const double rr = col_sum(prr, nrt, c);
     if (threadIdx.x == 0) {
@@ -989,6 +999,28 @@ __global__ __launch_bounds__(RED) void k_kappa_final(const double *part, int np,
     if (threadIdx.x == 0) kappa[0] = s[0] > 0.0 ? s[0] : 1.0;
 }
 
+// Gate of a batched head at the end of a replayed chunk: 1 while any column
+// is active.  The next chunk's kernels read it before doing anything, so a
+// head that has converged costs the replays still queued only their
+// launches.  out (optional) receives (gate, breakdown flag) for the host.
+__global__ __launch_bounds__(RED) void k_gate(const int32_t *active, int ldp, const int32_t *flag,
+                                             int32_t *gate, int32_t *out) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int a = 0;
+    for (int c = threadIdx.x; c < ldp; c += RED) a |= active[c] != 0;
+    if (a) atomicOr(&any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *gate = any;
+        if (out) {
+            out[0] = any;
+            out[1] = *flag;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Tile table and dispatch
 
@@ -1050,7 +1082,8 @@ int auto_tile(int ldp) {
 // walks its unit's whole row range, so blocks that only start when earlier
 // ones have finished would sweep the range a second time, behind the first
 // front, and fetch every shared neighbour row again.
-Geom make_geom(int n, int ldp, int tile, int resident = 0) {
+constexpr int SLAB_STEPS = 64;
+Geom make_geom(int n, int ldp, int tile, int resident = 0, int slabs = 1) {
     const TileCfg &t = kTiles[tile];
     const int cw = 2 * t.lpr * t.nv;
     const int rstep = WAVES * (64 / t.lpr);
@@ -1072,6 +1105,7 @@ Geom make_geom(int n, int ldp, int tile, int resident = 0) {
         if (g.nrt < 1) g.nrt = 1;
         g.nb = g.ncc * g.nrt;
         g.nb_pad = ((g.nb + 7) / 8) * 8;
+        g.slabs = 1;
     } else {
         g.P = g.ncc >= 8 ? 1 : 8 / g.ncc;          // row parts per column chunk
         g.U = g.ncc * g.P;                         // units (chunk, part)
@@ -1081,7 +1115,12 @@ Geom make_geom(int n, int ldp, int tile, int resident = 0) {
         if (B < 1) B = 1;
         if (B > groups) B = groups;
         g.B = B;
-        g.nrt = g.P * B;
+        // a slab spans at least SLAB_STEPS steps of the front: shorter sweeps
+        // do not drift, and each slab costs a launch
+        const int part = (n + g.P - 1) / g.P;
+        g.slabs = std::max(1, std::min(slabs, part / (B * rstep * SLAB_STEPS)));
+        g.slab = (part + g.slabs - 1) / g.slabs;
+        g.nrt = g.slabs * g.P * B;
         g.nb = ((g.U + 7) / 8) * 8 * B;            // units padded to XCD multiples
         g.nb_pad = g.nb;
     }
@@ -1123,20 +1162,36 @@ int resident_blocks(GK k, int tile) {
     return r;
 }
 
+// The SpMM of the solve runs as SPMM_SLABS launches, each over one slab of
+// every unit's rows: the unit's blocks walk their rows as one front, but over
+// a long range they drift apart and the neighbour rows they share leave L2
+// between uses; a kernel boundary every slab lines the front up again.  On
+// the 1 mm sphere (256 columns) 8 slabs took the SpMM from 5.60 to 5.43 ms
+// (4: 5.43, 16: 5.47).  Slabs never change a result: the dot products are
+// summed on fixed grids.
+constexpr int MAX_SLABS = 16;
+constexpr int SPMM_SLABS = 8;
+int spmm_slabs(GK k) {
+    return (k == GK::SPMM_SR || k == GK::SPMM_DOT64 || k == GK::SPMM_DOT32) ? SPMM_SLABS : 1;
+}
+
 Geom make_geom_for(GK k, int n, int ldp, int tile) {
-    return make_geom(n, ldp, tile, resident_blocks(k, tile));
+    return make_geom(n, ldp, tile, resident_blocks(k, tile), std::min(MAX_SLABS, spmm_slabs(k)));
 }
 
 template <int LPR, int NV, class TV, class TX>
 void launch_spmm(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t *ci,
                  const TV *va, const TX *X, TX *Y, double *part,
                  const double *bound = nullptr) {
-    if (part)
-        hipLaunchKernelGGL((k_spmm<LPR, NV, TV, TX, true>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g,
-                           rp, ci, va, X, Y, part, bound);
-    else
-        hipLaunchKernelGGL((k_spmm<LPR, NV, TV, TX, false>), dim3(g.nb_pad), dim3(BLOCK), 0, s,
-                           g, rp, ci, va, X, Y, part, bound);
+    Geom gs = g;
+    for (gs.cur = 0; gs.cur < g.slabs; ++gs.cur) {
+        if (part)
+            hipLaunchKernelGGL((k_spmm<LPR, NV, TV, TX, true>), dim3(g.nb_pad), dim3(BLOCK), 0, s,
+                               gs, rp, ci, va, X, Y, part, bound);
+        else
+            hipLaunchKernelGGL((k_spmm<LPR, NV, TV, TX, false>), dim3(g.nb_pad), dim3(BLOCK), 0,
+                               s, gs, rp, ci, va, X, Y, part, bound);
+    }
 }
 
 template <int LPR, int NV, class TP>
@@ -1150,8 +1205,10 @@ template <int LPR, int NV>
 void launch_spmm_sr(const Geom &g, hipStream_t s, const int32_t *rp, const int32_t *ci,
                     const double *vs, const double *dinv, const double *R, const double *beta,
                     double *S, double *part, const double *bound) {
-    hipLaunchKernelGGL((k_spmm_sr<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, rp, ci, vs,
-                       dinv, R, beta, S, part, bound);
+    Geom gs = g;
+    for (gs.cur = 0; gs.cur < g.slabs; ++gs.cur)
+        hipLaunchKernelGGL((k_spmm_sr<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, gs, rp, ci,
+                           vs, dinv, R, beta, S, part, bound);
 }
 
 template <int LPR, int NV>
@@ -1179,28 +1236,44 @@ void occupancy_of(GK k, int *out) {
 // cooperative front of 32 lanes x 2 pairs per row (128-column chunks), the
 // fastest for it on the 2 mm sphere, whatever tile the SpMM uses.
 constexpr int FLUSH_TILE = 13;   // lpr32_nv2_cw128_front
-// Residual update, direction update and residual b - A x: the same fixed
-// geometry (32 lanes x 2 pairs per row, 128-column front chunks).
-constexpr int STREAM_TILE = FLUSH_TILE;
+// Residual update, direction update, residual b - A x and the lazy-P flush
+// run with one geometry for a given column count, whatever the SpMM tile:
+// 128-column front chunks of 32 lanes x 2 pairs from 128 columns up, else
+// the narrowest front tile that holds every column (no idle lanes on
+// 32-96 column blocks).
+int stream_tile(int ldp) { return ldp >= 128 ? FLUSH_TILE : auto_tile(ldp); }
 static_assert(kTiles[FLUSH_TILE].lpr == 32 && kTiles[FLUSH_TILE].nv == 2 &&
                   kTiles[FLUSH_TILE].front == 1,
               "flush geometry");
 
 template <class TP>
-void launch_xflush(int n, int ldp, hipStream_t s, int cnt, const double *alphas, Ring<TP> ring,
+void launch_xflush(int n, int ldp, const int32_t *gate, hipStream_t s, int cnt,
+                   const double *alphas, Ring<TP> ring,
                    double *X) {
     static const int res = resident_per_xcd(k_xflush<TP>);
-    const Geom g = make_geom(n, ldp, FLUSH_TILE, res);
+    Geom g = make_geom(n, ldp, FLUSH_TILE, res);
+    g.gate = gate;
     hipLaunchKernelGGL((k_xflush<TP>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas, ring,
                        X);
 }
 
-void launch_pflush(int n, int ldp, hipStream_t s, int cnt, const double *alphas,
-                   const double *betas, Ring<double> ring, const double *dinv, double *P, double *X) {
-    static const int res = resident_per_xcd(k_pflush<32, 2>);
-    const Geom g = make_geom(n, ldp, FLUSH_TILE, res);
-    hipLaunchKernelGGL((k_pflush<32, 2>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
+template <int LPR, int NV>
+void launch_pflush_t(int n, int ldp, int tile, const int32_t *gate, hipStream_t s, int cnt,
+                     const double *alphas, const double *betas, Ring<double> ring,
+                     const double *dinv, double *P, double *X) {
+    static const int res = resident_per_xcd(k_pflush<LPR, NV>);
+    Geom g = make_geom(n, ldp, tile, res);
+    g.gate = gate;
+    hipLaunchKernelGGL((k_pflush<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, cnt, alphas,
                        betas, ring, dinv, P, X);
+}
+
+void launch_pflush(int n, int ldp, const int32_t *gate, hipStream_t s, int cnt,
+                   const double *alphas, const double *betas, Ring<double> ring,
+                   const double *dinv, double *P, double *X) {
+    const int tile = stream_tile(ldp);
+    ZI_TILE_SWITCH(tile, launch_pflush_t, n, ldp, tile, gate, s, cnt, alphas, betas, ring, dinv,
+                   P, X);
 }
 
 template <int LPR, int NV, class TP>
@@ -1253,6 +1326,7 @@ struct zi_solver_ws {
     double *vs = nullptr;                                     // values of A D^-1
     double *part[3] = {nullptr, nullptr, nullptr};   // 2 x nrt x ldp each (two folds)
     double *kap = nullptr;      // kappa and its block partial maxima
+    int32_t *gate = nullptr;    // batched heads: any column active at the last chunk end
     double *sc_d = nullptr;     // rho alpha beta bb rr tt bd (7 ldp)
     int32_t *sc_i = nullptr;    // iters active (2 ldp) + flag
     std::vector<hipEvent_t> ev;
@@ -1300,6 +1374,7 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
         (st = ws->pool.alloc(&ws->dinv, (size_t)sys->n)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->sc_d, (size_t)7 * ldp)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->kap, (size_t)KAPPA_BLOCKS + 1)) != ZI_OK ||
+        (st = ws->pool.alloc(&ws->gate, 1)) != ZI_OK ||
         (st = ws->pool.alloc(&ws->sc_i, (size_t)2 * ldp + 1)) != ZI_OK) {
         delete ws;
         return st;
@@ -1323,11 +1398,13 @@ zi_status ensure_ws(zi_system *sys, int ldp, int nrt_max) {
     return ZI_OK;
 }
 
+// Partial-sum rows per column that any geometry of these sizes uses: a
+// residency cap only lowers B, and slabs multiply P B by at most MAX_SLABS.
 int max_nrt(int n, int ldp) {
     int m = 1;
     for (int t = 0; t < NTILES; ++t) {
-        Geom g = make_geom(n, ldp, t);
-        if (g.nrt > m) m = g.nrt;
+        const Geom g = make_geom(n, ldp, t);
+        m = std::max(m, g.front ? MAX_SLABS * g.nrt : g.nrt);
     }
     return m;
 }
@@ -1361,7 +1438,10 @@ struct SolveCtx {
     Geom gu{};                // residual update; partials of red_beta
     Geom gp{};                // direction update (classic form)
     Geom gr{};                // residual b - A x; partials of red_init, red_refine
+    int32_t *gate = nullptr;      // batched heads: the head's gate (null: not gated)
+    int32_t *gate_out = nullptr;  // batched heads: (gate, breakdown) for the host
     int tile = 0, ldp = 0, L = 0, maxit = 0, check = 0;
+    int stile = 0;            // the streaming kernels' tile (a function of ldp)
     double tol = 0, tol2 = 0;
     double eta2 = 0;          // inner-cycle reduction (squared); 0 = run to tol
     bool mixed = false, timing = false;
@@ -1389,6 +1469,13 @@ struct SolveCtx {
     double *Rsr(int k) const { return k % LAZY == 0 ? ws->R : ws->P[k % LAZY]; }
     double *beta_slot(int k) const { return ws->bring + (size_t)(k % LAZY) * ldp; }
 };
+
+// A batched head's gate is opened for work the host enqueues outside the
+// replays (set-up, refinement, the final flush and residual); k_gate then
+// sets it from the active flags.
+zi_status open_gate(SolveCtx &c, hipStream_t s) {
+    return c.gate ? fill_i32(c.gate, 1, 1, s) : ZI_OK;
+}
 
 // The active flags (ldp) and the breakdown flag are adjacent: one copy into
 // the workspace's pinned buffer, read after the stream has been synchronised.
@@ -1458,13 +1545,14 @@ zi_status enqueue_flush(SolveCtx &c, int it_end, hipStream_t s) {
         Timed t(c, 3, s, cnt == LAZY);
         ZI_TRY(t.st);
         if (first == 0) {
-            launch_xflush<TP>(c.sys->n, c.ldp, s, cnt, (const double *)al, ring, c.ws->X);
+            launch_xflush<TP>(c.sys->n, c.ldp, c.gate, s, cnt, (const double *)al, ring,
+                              c.ws->X);
         } else {
             // the step lengths are rotated into a contiguous scratch block
             for (int j = 0; j < cnt; ++j)
                 ZI_HIP(hipMemcpyAsync(c.ws->aflush + (size_t)j * c.ldp, c.alpha(c.flushed + j),
                                       sizeof(double) * c.ldp, hipMemcpyDeviceToDevice, s));
-            launch_xflush<TP>(c.sys->n, c.ldp, s, cnt, (const double *)c.ws->aflush, ring,
+            launch_xflush<TP>(c.sys->n, c.ldp, c.gate, s, cnt, (const double *)c.ws->aflush, ring,
                               c.ws->X);
         }
     }
@@ -1499,9 +1587,9 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
     {
         Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
-        launch_update<32, 2, TP>(c.gu, s, (const double *)al, (const double *)ws->dinv,
-                                 (const TP *)ws->R, (const TP *)Q, reinterpret_cast<TP *>(ws->R),
-                                 ws->part[1], ws->part[2]);
+        ZI_TILE_SWITCH(c.stile, launch_update, c.gu, s, (const double *)al,
+                       (const double *)ws->dinv, (const TP *)ws->R, (const TP *)Q,
+                       reinterpret_cast<TP *>(ws->R), ws->part[1], ws->part[2]);
     }
     if ((k + 1) % LAZY == 0 || replace_r) ZI_TRY(enqueue_flush<TP>(c, k + 1, s));
     // a reliable update rewrites the partials of part[0..2] with c.gr's layout
@@ -1512,8 +1600,8 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
     {
         Timed t(c, 2, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
-        launch_pupdate<32, 2, TP>(c.gp, s, (const double *)c.sc.beta, (const double *)ws->dinv,
-                                  (const TP *)ws->R, (const TP *)Pk, Pn);
+        ZI_TILE_SWITCH(c.stile, launch_pupdate, c.gp, s, (const double *)c.sc.beta,
+                       (const double *)ws->dinv, (const TP *)ws->R, (const TP *)Pk, Pn);
     }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
@@ -1540,7 +1628,7 @@ zi_status enqueue_flush_sr(SolveCtx &c, int it_end, hipStream_t s) {
     {
         Timed t(c, 2, s, cnt == LAZY);
         ZI_TRY(t.st);
-        launch_pflush(c.sys->n, c.ldp, s, cnt, al, bt, ring, (const double *)c.ws->dinv,
+        launch_pflush(c.sys->n, c.ldp, c.gate, s, cnt, al, bt, ring, (const double *)c.ws->dinv,
                       c.ws->P[0], c.ws->X);
     }
     ZI_HIP(hipGetLastError());
@@ -1574,9 +1662,9 @@ zi_status enqueue_iteration_sr(SolveCtx &c, int k, hipStream_t s) {
     {
         Timed t(c, 1, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
-        launch_update<32, 2, double>(c.gu, s, (const double *)al, (const double *)ws->dinv,
-                                     (const double *)c.Rsr(k), (const double *)ws->Q,
-                                     c.Rsr(k + 1), ws->part[1], ws->part[2]);
+        ZI_TILE_SWITCH(c.stile, launch_update, c.gu, s, (const double *)al,
+                       (const double *)ws->dinv, (const double *)c.Rsr(k),
+                       (const double *)ws->Q, c.Rsr(k + 1), ws->part[1], ws->part[2]);
     }
     hipLaunchKernelGGL(k_red_beta, dim3(c.ldp), dim3(RED), 0, s, c.sc, ws->part[1], ws->part[2],
                        c.gu.nrt, c.beta_slot(k + 1), 1);
@@ -1614,13 +1702,13 @@ zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r) {
     ZI_TILE_SWITCH(c.tile, launch_spmm, c.g, s, c.sys->sp_ptr, c.sys->sp_col,
                    (const double *)c.sys->sp_val, (const double *)ws->X, ws->Q, (double *)nullptr);
     if (c.mixed) {   // R holds float32 in the mixed mode
-        launch_residual<32, 2, float>(c.gr, s, c.sys, (const int32_t *)c.colmap, ws->dinv, ws->Q,
-                                      write_r ? reinterpret_cast<float *>(ws->R) : nullptr,
-                                      ws->part[0], ws->part[1], ws->part[2]);
+        ZI_TILE_SWITCH(c.stile, launch_residual, c.gr, s, c.sys, (const int32_t *)c.colmap,
+                       ws->dinv, ws->Q, write_r ? reinterpret_cast<float *>(ws->R) : nullptr,
+                       ws->part[0], ws->part[1], ws->part[2]);
     } else {
-        launch_residual<32, 2, double>(c.gr, s, c.sys, (const int32_t *)c.colmap, ws->dinv,
-                                       ws->Q, write_r ? ws->R : nullptr, ws->part[0],
-                                       ws->part[1], ws->part[2]);
+        ZI_TILE_SWITCH(c.stile, launch_residual, c.gr, s, c.sys, (const int32_t *)c.colmap,
+                       ws->dinv, ws->Q, write_r ? ws->R : nullptr, ws->part[0], ws->part[1],
+                       ws->part[2]);
     }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
@@ -1630,13 +1718,13 @@ zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r) {
 zi_status enqueue_restart_direction(SolveCtx &c, hipStream_t s) {
     if (c.mixed) {
         float *p = c.P<float>(c.it);
-        launch_pupdate<32, 2, float>(c.gp, s, (const double *)nullptr, (const double *)c.ws->dinv,
-                                     (const float *)c.ws->R, (const float *)p, p);
+        ZI_TILE_SWITCH(c.stile, launch_pupdate, c.gp, s, (const double *)nullptr,
+                       (const double *)c.ws->dinv, (const float *)c.ws->R, (const float *)p, p);
     } else {
         double *p = c.P<double>(c.it);
-        launch_pupdate<32, 2, double>(c.gp, s, (const double *)nullptr,
-                                      (const double *)c.ws->dinv, (const double *)c.ws->R,
-                                      (const double *)p, p);
+        ZI_TILE_SWITCH(c.stile, launch_pupdate, c.gp, s, (const double *)nullptr,
+                       (const double *)c.ws->dinv, (const double *)c.ws->R, (const double *)p,
+                       p);
     }
     ZI_HIP(hipGetLastError());
     return ZI_OK;
@@ -1654,7 +1742,7 @@ int pick_tile(const zi_system *sys, int ldp, int precision, int requested) {
 // graphs: the iterations will be replayed as captured chunks (zi_solve_impl
 // with opts.graph, and every batch).
 zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipStream_t s,
-                      bool graphs) {
+                      bool graphs, bool gated = false) {
     c.t_start = std::chrono::steady_clock::now();
     const int n = sys->n;
     const int L = o->columns ? o->n_columns : sys->L;
@@ -1707,9 +1795,15 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     c.ws = ws;
     c.g = make_geom_for(c.sr ? GK::SPMM_SR : c.mixed ? GK::SPMM_DOT32 : GK::SPMM_DOT64, n, ldp,
                         tile);
-    c.gu = make_geom_for(c.mixed ? GK::UPDATE32 : GK::UPDATE64, n, ldp, STREAM_TILE);
-    c.gp = make_geom_for(c.mixed ? GK::PUPDATE32 : GK::PUPDATE64, n, ldp, STREAM_TILE);
-    c.gr = make_geom_for(c.mixed ? GK::RESIDUAL32 : GK::RESIDUAL64, n, ldp, STREAM_TILE);
+    c.stile = stream_tile(ldp);
+    c.gu = make_geom_for(c.mixed ? GK::UPDATE32 : GK::UPDATE64, n, ldp, c.stile);
+    c.gp = make_geom_for(c.mixed ? GK::PUPDATE32 : GK::PUPDATE64, n, ldp, c.stile);
+    c.gr = make_geom_for(c.mixed ? GK::RESIDUAL32 : GK::RESIDUAL64, n, ldp, c.stile);
+    if (gated) {
+        c.gate = ws->gate;
+        c.g.gate = c.gu.gate = c.gp.gate = c.gr.gate = c.gate;
+        ZI_TRY(open_gate(c, s));
+    }
     c.tile = tile;
     c.ldp = ldp;
     c.L = L;
@@ -1742,6 +1836,7 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     sc.tt = ws->sc_d + 5 * ldp;
     sc.bd = ws->sc_d + 6 * ldp;
     sc.kappa = ws->kap;
+    sc.gate = c.gate;
     sc.iters = ws->sc_i;
     sc.active = ws->sc_i + ldp;
     sc.flag = ws->sc_i + 2 * ldp;
@@ -1761,14 +1856,13 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
         ZI_TRY(true_residual(c, s, true));
     } else {
         if (c.mixed) {
-            launch_residual<32, 2, float>(c.gr, s, sys, (const int32_t *)c.colmap, ws->dinv,
-                                          (const double *)nullptr,
-                                          reinterpret_cast<float *>(ws->R), ws->part[0],
-                                          ws->part[1], ws->part[2]);
+            ZI_TILE_SWITCH(c.stile, launch_residual, c.gr, s, sys, (const int32_t *)c.colmap,
+                           ws->dinv, (const double *)nullptr, reinterpret_cast<float *>(ws->R),
+                           ws->part[0], ws->part[1], ws->part[2]);
         } else {
-            launch_residual<32, 2, double>(c.gr, s, sys, (const int32_t *)c.colmap, ws->dinv,
-                                           (const double *)nullptr, ws->R, ws->part[0],
-                                           ws->part[1], ws->part[2]);
+            ZI_TILE_SWITCH(c.stile, launch_residual, c.gr, s, sys, (const int32_t *)c.colmap,
+                           ws->dinv, (const double *)nullptr, ws->R, ws->part[0], ws->part[1],
+                           ws->part[2]);
         }
     }
     hipLaunchKernelGGL(k_red_init, dim3(ldp), dim3(RED), 0, s, sc, ws->part[0], ws->part[1],
@@ -1786,6 +1880,9 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     } else {
         ZI_TRY(enqueue_restart_direction(c, s));
     }
+    if (c.gate)
+        hipLaunchKernelGGL(k_gate, dim3(1), dim3(RED), 0, s, (const int32_t *)sc.active, ldp,
+                           (const int32_t *)sc.flag, c.gate, (int32_t *)nullptr);
     ZI_TRY(read_active(c, s));
     c.done = !c.any_active;
     return ZI_OK;
@@ -1799,10 +1896,14 @@ zi_status solve_after_converged(SolveCtx &c, hipStream_t s) {
         c.done = true;
         return ZI_OK;
     }
+    ZI_TRY(open_gate(c, s));
     ZI_TRY(flush_all(c, s));
     ZI_TRY(true_residual(c, s, true));
     hipLaunchKernelGGL(k_red_refine, dim3(c.ldp), dim3(RED), 0, s, c.sc, c.ws->part[1],
                        c.ws->part[2], c.gr.nrt, c.L, c.tol2, c.eta2);
+    if (c.gate)
+        hipLaunchKernelGGL(k_gate, dim3(1), dim3(RED), 0, s, (const int32_t *)c.sc.active, c.ldp,
+                           (const int32_t *)c.sc.flag, c.gate, (int32_t *)nullptr);
     ZI_HIP(hipGetLastError());
     ZI_TRY(read_active(c, s));
     if (!c.any_active) {
@@ -1833,6 +1934,7 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
     const int n = c.sys->n, L = c.L, ldp = c.ldp;
     const bool timing = c.timing;
     c.timing = false;
+    ZI_TRY(open_gate(c, s));
     ZI_TRY(flush_all(c, s));
     c.timing = timing;
     ZI_TRY(gather_rows(ws->X, ldp, c.sys->iperm, T, L, n, L, s));
@@ -1927,6 +2029,13 @@ struct GraphSet {
         clear();
         ex.assign(c.mixed ? MIXED_REPLACE / c.check : 1, nullptr);
     }
+    // As reset, but the old graphs may still be executing (a replay is kept
+    // queued): they go to `grave`, destroyed once the stream has drained.
+    void retire(const SolveCtx &c, std::vector<hipGraphExec_t> &grave) {
+        for (auto e : ex)
+            if (e) grave.push_back(e);
+        ex.assign(c.mixed ? MIXED_REPLACE / c.check : 1, nullptr);
+    }
     static int phase(const SolveCtx &c) {
         return c.mixed ? (c.it % MIXED_REPLACE) / c.check : 0;
     }
@@ -1950,6 +2059,10 @@ zi_status capture_graph(std::vector<SolveCtx *> &cs, std::vector<hipStream_t> &s
         const int flushed = cs[k]->flushed;
         st = enqueue_iterations(*cs[k], count, streams[k]);
         cs[k]->flushed = flushed;   // the replays, not the capture, advance it
+        if (st == ZI_OK && cs[k]->gate)
+            hipLaunchKernelGGL(k_gate, dim3(1), dim3(RED), 0, streams[k],
+                               (const int32_t *)cs[k]->sc.active, cs[k]->ldp,
+                               (const int32_t *)cs[k]->sc.flag, cs[k]->gate, cs[k]->gate_out);
         if (st == ZI_OK && hipEventRecord(joins[k], streams[k]) != hipSuccess) st = ZI_EDEVICE;
         if (st == ZI_OK && hipStreamWaitEvent(origin, joins[k], 0) != hipSuccess) st = ZI_EDEVICE;
     }
@@ -2028,20 +2141,42 @@ zi_status zi_solve_impl(zi_system *sys, const zi_solve_opts *o, double *T, zi_so
 
 zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_solve_opts *o,
                               double *const *T, zi_solve_stats *st, hipStream_t s) {
+    // (gate, breakdown flag) of every head after a replay, and two pinned
+    // host copies: the host reads one replay's copy while the next runs.
+    int32_t *gates_d = nullptr, *gates_h = nullptr;
+    ZI_HIP(hipMalloc(reinterpret_cast<void **>(&gates_d), sizeof(int32_t) * 2 * nsys));
+    if (hipHostMalloc(reinterpret_cast<void **>(&gates_h), sizeof(int32_t) * 4 * nsys) !=
+        hipSuccess) {
+        (void)hipFree(gates_d);
+        set_error("hipHostMalloc of the batch flags failed");
+        return ZI_ENOMEM;
+    }
+    struct Bufs {
+        int32_t *d, *h;
+        ~Bufs() {
+            (void)hipFree(d);
+            (void)hipHostFree(h);
+        }
+    } bufs{gates_d, gates_h};
     std::vector<SolveCtx> cs(nsys);
     for (int k = 0; k < nsys; ++k) {
-        ZI_TRY(solve_begin(systems[k], o, cs[k], s, true));
+        ZI_TRY(solve_begin(systems[k], o, cs[k], s, true, true));
         cs[k].timing = false;   // events cannot be captured
+        cs[k].gate_out = gates_d + 2 * k;
     }
-    // Heads are captured in groups of BATCH_GROUP: when a head finishes, only
-    // its group's graph is captured again.  Each group's graph is launched on
-    // a stream of its own, forked from and joined back to the caller's stream.
+    ZI_TRY(fill_i32(gates_d, 0, (size_t)2 * nsys, s));
+    // Heads are captured in groups of BATCH_GROUP, each group's graph launched
+    // on a stream of its own, forked from and joined back to the caller's
+    // stream.  A head that has converged stays in its group's graph, gated
+    // (its kernels return at once), so finishing heads cost no new capture; a
+    // group is captured again only for a head that is not in its graph or
+    // whose iteration phase moved (a refinement restart).
     constexpr int BATCH_GROUP = 8;
     const int ngroups = (nsys + BATCH_GROUP - 1) / BATCH_GROUP;
     // one stream per system (capture branches), per group (launch) + capture origin
     std::vector<hipStream_t> streams(nsys + ngroups + 1);
     for (auto &x : streams) ZI_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    std::vector<hipEvent_t> events(ngroups + 1);   // joins, fork
+    std::vector<hipEvent_t> events(ngroups + 3);   // joins, fork, flags copied (2)
     for (auto &e : events) ZI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     hipStream_t cap = streams[nsys + ngroups];
     struct Guard {
@@ -2054,47 +2189,51 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
     } guard{streams, events};
     const int chunk = cs[0].check;   // same options for every system
     std::vector<GraphSet> gsets(ngroups);
+    std::vector<hipGraphExec_t> grave;   // replaced graphs, destroyed after the last sync
     std::vector<std::vector<int>> last(ngroups);
-    std::vector<int> members, gm;
+    std::vector<int> epoch(nsys, 0);   // bumped when the host restarts a head (refinement)
+    struct Replay {
+        bool live = false;
+        std::vector<int> heads, epochs;
+    } rp[2];
     zi_status r = ZI_OK;
-    for (;;) {
-        members.clear();
+
+    auto members = [&]() {
+        std::vector<int> m;
         for (int k = 0; k < nsys; ++k)
-            if (!cs[k].done && cs[k].maxit - cs[k].it >= chunk) members.push_back(k);
-        // solves within one chunk of maxit finish on their own (no graph)
-        for (int k = 0; k < nsys && r == ZI_OK; ++k) {
-            if (cs[k].done || cs[k].maxit - cs[k].it >= chunk) continue;
-            while (!cs[k].done && r == ZI_OK) {
-                const int rest = cs[k].maxit - cs[k].it;
-                r = enqueue_iterations(cs[k], rest, s);
-                cs[k].it += rest;
-                if (r == ZI_OK) r = solve_check(cs[k], s);
-            }
-        }
-        if (r != ZI_OK || members.empty()) break;
-        if (hipEventRecord(events[ngroups], s) != hipSuccess) {
-            r = ZI_EDEVICE;
-            break;
-        }
-        for (int grp = 0; grp < ngroups && r == ZI_OK; ++grp) {
+            if (!cs[k].done && cs[k].maxit - cs[k].it >= chunk) m.push_back(k);
+        return m;
+    };
+    // Replay one chunk of every member (all groups), then copy the flags.
+    auto launch = [&](const std::vector<int> &mem, int p) -> zi_status {
+        std::vector<int> gm;
+        ZI_HIP(hipEventRecord(events[ngroups], s));
+        for (int grp = 0; grp < ngroups; ++grp) {
             gm.clear();
-            for (int k : members)
+            for (int k : mem)
                 if (k / BATCH_GROUP == grp) gm.push_back(k);
             if (gm.empty()) continue;
-            if (gm != last[grp]) {   // members share the iteration count (and phase)
-                gsets[grp].reset(cs[gm[0]]);
+            bool covered = !last[grp].empty();
+            for (int k : gm)
+                covered = covered &&
+                          std::find(last[grp].begin(), last[grp].end(), k) != last[grp].end();
+            // the graph's active heads advance together: the first gives the phase
+            const int ph = GraphSet::phase(cs[gm[0]]);
+            if (covered && !gsets[grp].ex[ph] && gm != last[grp])
+                covered = false;   // a new capture leaves the converged heads out
+            if (!covered) {   // the last replay may still run the old graphs
+                gsets[grp].retire(cs[gm[0]], grave);
                 last[grp] = gm;
             }
-            hipGraphExec_t &exec = gsets[grp].ex[GraphSet::phase(cs[gm[0]])];
+            hipGraphExec_t &exec = gsets[grp].ex[ph];
             if (!exec) {
                 std::vector<SolveCtx *> sel;
                 std::vector<hipStream_t> ss;
-                for (int k : gm) {
+                for (int k : last[grp]) {
                     sel.push_back(&cs[k]);
                     ss.push_back(streams[k]);
                 }
-                r = capture_graph(sel, ss, chunk, cap, &exec);
-                if (r != ZI_OK) break;
+                ZI_TRY(capture_graph(sel, ss, chunk, cap, &exec));
             }
             hipStream_t ls = streams[nsys + grp];
             if (hipStreamWaitEvent(ls, events[ngroups], 0) != hipSuccess ||
@@ -2102,31 +2241,88 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
                 hipEventRecord(events[grp], ls) != hipSuccess ||
                 hipStreamWaitEvent(s, events[grp], 0) != hipSuccess) {
                 set_error("hipGraphLaunch failed");
-                r = ZI_EDEVICE;
+                return ZI_EDEVICE;
             }
         }
-        if (r != ZI_OK) break;
-        // every member's flags in one synchronisation
-        for (int k : members) {
+        for (int k : mem) {
             cs[k].it += chunk;
-            cs[k].flushed = cs[k].it;
-            r = enqueue_read_active(cs[k], s);
-            if (r != ZI_OK) break;
+            cs[k].flushed = cs[k].it;   // every chunk ends on a flush
         }
+        ZI_HIP(hipMemcpyAsync(gates_h + (size_t)p * 2 * nsys, gates_d,
+                              sizeof(int32_t) * 2 * nsys, hipMemcpyDeviceToHost, s));
+        ZI_HIP(hipEventRecord(events[ngroups + 1 + p], s));
+        rp[p].live = true;
+        rp[p].heads = mem;
+        rp[p].epochs.clear();
+        for (int k : mem) rp[p].epochs.push_back(epoch[k]);
+        return ZI_OK;
+    };
+    // Solves within one chunk of maxit finish on their own (no graph).
+    auto tails = [&]() -> zi_status {
+        for (int k = 0; k < nsys; ++k) {
+            if (cs[k].done || cs[k].maxit - cs[k].it >= chunk) continue;
+            ZI_TRY(open_gate(cs[k], s));
+            while (!cs[k].done) {
+                const int rest = cs[k].maxit - cs[k].it;
+                ZI_TRY(enqueue_iterations(cs[k], rest, s));
+                cs[k].it += rest;
+                ZI_TRY(solve_check(cs[k], s));
+            }
+        }
+        return ZI_OK;
+    };
+
+    int par = 0;
+    r = tails();
+    if (r == ZI_OK) {
+        const std::vector<int> m = members();
+        if (!m.empty()) r = launch(m, par);
+    }
+    while (r == ZI_OK && rp[par].live) {
+        // The next replay is queued before this one's flags are read, with the
+        // members as known now: a head found converged below is still in it,
+        // gated, and costs only its launches.
+        const std::vector<int> next = members();
+        if (!next.empty()) r = launch(next, par ^ 1);
         if (r != ZI_OK) break;
-        if (hipStreamSynchronize(s) != hipSuccess) {
-            set_error("hipStreamSynchronize failed");
+        if (hipEventSynchronize(events[ngroups + 1 + par]) != hipSuccess) {
+            set_error("hipEventSynchronize failed");
             r = ZI_EDEVICE;
             break;
         }
-        for (int k : members) {
-            take_active(cs[k]);
+        const int32_t *gh = gates_h + (size_t)par * 2 * nsys;
+        for (size_t j = 0; j < rp[par].heads.size() && r == ZI_OK; ++j) {
+            const int k = rp[par].heads[j];
+            // flags of a replay launched before the head was restarted are stale
+            if (cs[k].done || rp[par].epochs[j] != epoch[k]) continue;
+            cs[k].any_active = gh[2 * k] != 0;
+            cs[k].h_flag = gh[2 * k + 1];
+            if (!cs[k].any_active && rp[par ^ 1].live) {
+                const auto &q = rp[par ^ 1].heads;
+                if (std::find(q.begin(), q.end(), k) != q.end()) {
+                    // the queued replay found the head's gate closed and did
+                    // nothing for it: its iteration count (which fixes the
+                    // ring slots and the reliable-update phase) goes back
+                    cs[k].it -= chunk;
+                    cs[k].flushed = cs[k].it;
+                    last[k / BATCH_GROUP].clear();   // its group is captured again
+                }
+            }
+            const int ref = cs[k].refinements;
             r = solve_check_taken(cs[k], s);
-            if (r != ZI_OK) break;
+            if (cs[k].refinements != ref) ++epoch[k];
         }
-        if (r != ZI_OK) break;
+        rp[par].live = false;
+        if (r == ZI_OK) r = tails();
+        par ^= 1;
+        if (r == ZI_OK && !rp[par].live) {   // nothing queued: heads restarted since
+            const std::vector<int> m = members();
+            if (!m.empty()) r = launch(m, par);
+        }
     }
+    (void)hipStreamSynchronize(s);   // no replay left running before graphs are destroyed
     for (auto &g : gsets) g.clear();
+    for (auto e : grave) (void)hipGraphExecDestroy(e);
     ZI_TRY(r);
     zi_status worst = ZI_OK;
     for (int k = 0; k < nsys; ++k) {
