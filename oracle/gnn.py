@@ -8,11 +8,16 @@ Graph: the mesh graph without self loops, aggregated with the symmetric
 normalisation Ahat = D^-1/2 Adj D^-1/2 (D = node degrees), so the transpose
 needed by the backward pass is Ahat itself.
 
-Layer k (k = 0..K-1) maps H_k (n x F_k) to
+Layer k (k = 0..K-1) with h_k aggregation hops (h_k >= 1) maps H_k
+(n x F_k) to
 
-    M_k     = Ahat H_k
+    M_k     = Ahat^(h_k) H_k     (Ahat applied h_k times)
     Z_k     = H_k Ws_k + M_k Wn_k + b_k
     H_{k+1} = relu(Z_k)          (identity on the last layer)
+
+Layers with many hops see far across the mesh: the potential change that a
+conductivity perturbation causes is global, and polynomials in Ahat of high
+degree act on the smooth part of the mesh graph's spectrum.
 
 Prediction y = H_K[:, 0]; loss = sum_i (y_i - t_i)^2 / sum_i t_i^2.
 Parameters per layer: Ws (F_k x F_{k+1}), Wn (F_k x F_{k+1}), b (F_{k+1}).
@@ -45,13 +50,21 @@ def init_params(dims, seed):
     return params
 
 
-def forward(params, Ahat, X):
-    """Returns (prediction y, cache for backward)."""
+def aggregate(Ahat, H, hops):
+    """Ahat^hops H, one product at a time."""
+    M = H
+    for _ in range(hops):
+        M = Ahat @ M
+    return M
+
+
+def forward(params, Ahat, X, hops=None):
+    """Returns (prediction y, cache for backward); hops[k] per layer (1)."""
     H = X
     cache = []
     K = len(params)
     for k, p in enumerate(params):
-        M = Ahat @ H
+        M = aggregate(Ahat, H, hops[k] if hops else 1)
         Z = H @ p["Ws"] + M @ p["Wn"] + p["b"]
         cache.append((H, M, Z))
         H = np.maximum(Z, 0.0) if k < K - 1 else Z
@@ -62,7 +75,7 @@ def loss(y, t):
     return float(((y - t) ** 2).sum() / (t ** 2).sum())
 
 
-def backward(params, Ahat, cache, y, t):
+def backward(params, Ahat, cache, y, t, hops=None):
     """Gradients of the loss with respect to every parameter."""
     K = len(params)
     dH = np.zeros_like(cache[-1][2])
@@ -73,7 +86,7 @@ def backward(params, Ahat, cache, y, t):
         dZ = dH if k == K - 1 else dH * (Z > 0.0)
         grads[k] = dict(Ws=H.T @ dZ, Wn=M.T @ dZ, b=dZ.sum(axis=0))
         dM = dZ @ params[k]["Wn"].T
-        dH = dZ @ params[k]["Ws"].T + Ahat.T @ dM
+        dH = dZ @ params[k]["Ws"].T + aggregate(Ahat.T, dM, hops[k] if hops else 1)
     return grads
 
 

@@ -52,6 +52,40 @@ def test_gradients_match_finite_differences():
                 assert abs(fd - G[idx]) <= 1e-4 * max(1e-3, abs(fd)), (k, name, idx, fd, G[idx])
 
 
+def test_multi_hop_gradients_and_power():
+    # Layers aggregating over several hops: the aggregation equals the dense
+    # matrix power, and the gradients match central finite differences.
+    Ah, H = _graph()
+    rng = np.random.default_rng(4)
+    n = H.n
+    Hm = rng.normal(size=(n, 3))
+    dense = np.linalg.matrix_power(Ah.toarray(), 5)
+    np.testing.assert_allclose(gnn.aggregate(Ah, Hm, 5), dense @ Hm, rtol=1e-10, atol=1e-12)
+    hops = [1, 4, 2]
+    X = rng.normal(size=(n, 5))
+    t = rng.normal(size=n)
+    params = gnn.init_params([5, 8, 8, 1], seed=6)
+    y, cache = gnn.forward(params, Ah, X, hops)
+    grads = gnn.backward(params, Ah, cache, y, t, hops)
+    # a dropped hop in the backward pass would change these
+    y1, c1 = gnn.forward(params, Ah, X)
+    assert np.abs(y1 - y).max() > 1e-3
+    for k in range(3):
+        for name in ("Ws", "Wn", "b"):
+            P = params[k][name]
+            G = grads[k][name]
+            for idx in [tuple(rng.integers(0, s) for s in P.shape) for _ in range(4)]:
+                old = P[idx]
+                h = 1e-6 * max(1.0, abs(old))
+                P[idx] = old + h
+                lp = gnn.loss(gnn.forward(params, Ah, X, hops)[0], t)
+                P[idx] = old - h
+                lm = gnn.loss(gnn.forward(params, Ah, X, hops)[0], t)
+                P[idx] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - G[idx]) <= 1e-4 * max(1e-3, abs(fd)), (k, name, idx, fd, G[idx])
+
+
 def test_adam_training_reduces_loss():
     Ah, H = _graph()
     rng = np.random.default_rng(2)
