@@ -3,7 +3,9 @@ conductivity (log-normal, sd 0.2, smoothed with an 8 mm Gaussian).
 
 Generates training data with the method itself (mixed-precision transfer
 columns of random electrodes for random fields), trains the 6-layer mesh-graph
-network (hidden 64, float32) with the library's forward/backward kernels, and
+network (hidden 64, float32, layers aggregating over 1, 4, 16, 64, 16, 4 hops;
+features, targets and x0 from library kernels) with the library's
+forward/backward kernels, and
 reports PCG iterations and wall time to relative residual 1e-8 on held-out
 fields from x0 = 0, from the unperturbed head's transfer column, and from the
 network.  Prints one JSON line; progress goes to stderr.

@@ -286,7 +286,8 @@ zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y,
  * A K-layer network on the mesh graph of an assembled system (its CSR
  * structure), with the symmetric normalised aggregation
  * Ahat = D^-1/2 Adj D^-1/2.  Layer k maps H_k (n x dims[k]) to
- * relu(H_k Ws_k + (Ahat H_k) Wn_k + b_k) (no relu on the last layer); the
+ * relu(H_k Ws_k + (Ahat^h_k H_k) Wn_k + b_k) (no relu on the last layer, h_k
+ * aggregation hops, 1 when hops is NULL); the
  * prediction is column 0 of H_K.  float32 throughout; weight gradients are
  * reduced in float64 in a fixed order.  The network only proposes x0 for
  * zi_transfer_solve; the PCG always finishes to its tolerance.
@@ -295,6 +296,7 @@ zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y,
  * must be even and <= 64; dims[K] <= 64. */
 typedef struct zi_gnn zi_gnn;
 zi_status zi_gnn_create(const zi_system *sys, int32_t n_layers, const int32_t *dims /* HOST */,
+                        const int32_t *hops /* HOST, n_layers entries in 1..1024, or NULL */,
                         zi_gnn **out);
 int64_t zi_gnn_param_count(const zi_gnn *net);
 /* Parameters from / to HOST memory (setting resets the Adam moments). */
@@ -310,6 +312,37 @@ zi_status zi_gnn_loss_grad(zi_gnn *net, const float *X, const float *t, double *
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradients. */
 zi_status zi_gnn_adam_step(zi_gnn *net, float lr, void *hip_stream);
 void zi_gnn_destroy(zi_gnn *net);
+/* Input features of the warm-start network for electrode column l of a head
+ * whose conductivity differs from a base head's (same mesh, same electrodes):
+ * X (n_nodes x 10 float32, row-major), per node i,
+ *   0  b_il / max_i |b_il|              (the right-hand side, App. A.4)
+ *   1  log(a_ii / a0_ii)                (the conductivity change seen by node i)
+ *   2  t0_il / max_i |t0_il|            (the base head's transfer column)
+ *   3-5 x_i / radius
+ *   6  |x_i - centre| / radius          (distance to electrode l's centre)
+ *   7  log(a0_ii / max_j a0_jj)         (the base conductivity, a compartment mark)
+ *   8  r_i / max_i |r_i|, r = b_l - A t0_l   (the residual of t0 for this head)
+ *   9  1                               (a constant input)
+ * a and a0 the grounded matrices of `perturbed` and `base`; T0 the base
+ * transfer matrix (device, n_nodes x ldt, ldt >= L); centre HOST double[3].
+ * ZI_EINVAL for a different mesh or an electrode out of range. */
+zi_status zi_gnn_features(const zi_system *base, const zi_system *perturbed, const double *T0,
+                          int32_t ldt, int32_t electrode, const double *centre, double radius,
+                          float *X, void *hip_stream);
+/* Training target of the warm-start network for electrode l: with
+ * s_l = max_i |t0_il|, t_i = gain (T[i, col] - T0[i, l]) / s_l (n_nodes
+ * float32).  T (n_nodes x ldT) holds the head's transfer column col, T0 the
+ * base transfer matrix (n_nodes x ldt).  *sumsq (HOST, may be NULL) receives
+ * sum_i t_i^2. */
+zi_status zi_gnn_target(const double *T, int32_t ldT, int32_t col, const double *T0,
+                        int32_t ldt, int32_t electrode, double gain, int32_t n_nodes, float *t,
+                        double *sumsq, void *hip_stream);
+/* The proposed initial iterate from a prediction y (n_nodes float32, the
+ * network's output for the features of electrode l):
+ * x0[i * ldx + xcol] = T0[i, l] + s_l y_i / gain. */
+zi_status zi_gnn_x0(const float *y, const double *T0, int32_t ldt, int32_t electrode,
+                    double gain, int32_t n_nodes, double *x0, int32_t ldx, int32_t xcol,
+                    void *hip_stream);
 
 /* Measurement aid: copies n float64 values (n even, 16-byte aligned) from
  * src to dst with the 16-byte streaming accesses of the solver kernels and

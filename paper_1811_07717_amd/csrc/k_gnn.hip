@@ -3,8 +3,8 @@
 // The network runs on the mesh graph of the assembled system (the CSR
 // structure of A), aggregated with Ahat = D^-1/2 Adj D^-1/2 (diagonal entries
 // stored as zeros), which is symmetric, so the backward aggregation is the
-// same SpMM.  Layer k:  M = Ahat H,  Z = H Ws + M Wn + b,  H' = relu(Z)
-// (identity on the last layer); prediction y = H_K[:, 0]; loss
+// same SpMM.  Layer k with h_k hops:  M = Ahat^h_k H,  Z = H Ws + M Wn + b,
+// H' = relu(Z) (identity on the last layer); prediction y = H_K[:, 0]; loss
 // sum (y - t)^2 / sum t^2.  Weight gradients are reduced per block in float64
 // and across blocks in a fixed order, so training is bitwise reproducible.
 #include <cmath>
@@ -16,12 +16,13 @@ struct zi_gnn {
     const zi_system *sys = nullptr;
     int K = 0;
     std::vector<int> dims;
+    std::vector<int> hops;                 // aggregation hops per layer (>= 1)
     std::vector<int64_t> off_ws, off_wn, off_b;   // offsets into the flat parameter array
     int64_t nparam = 0;
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     float *ahat = nullptr;                 // nnz values on the system's CSR structure
     std::vector<float *> H, M;             // H[0..K], M[0..K-1]; H[0] is the input copy
-    float *dH = nullptr, *dZ = nullptr, *dM = nullptr, *tmp = nullptr;
+    float *dH = nullptr, *dZ = nullptr, *dM = nullptr, *tmp = nullptr, *tmp2 = nullptr;
     double *part = nullptr;                // weight-gradient partials
     int nblk = 0;
     double *lpart = nullptr;               // loss partials
@@ -219,13 +220,27 @@ zi_status wgrad(zi_gnn *g, const float *A, const float *D, int fin, int fout, fl
     return ZI_OK;
 }
 
+// out = Ahat^hops in (hops >= 1): one product at a time through the two
+// scratch blocks a and b, the last product written to out.
+zi_status aggregate(zi_gnn *g, const float *in, int hops, int fi, float *out, float *a, float *b,
+                    hipStream_t s) {
+    const int32_t n = g->sys->n;
+    const float *src = in;
+    for (int h = 0; h < hops; ++h) {
+        float *dst = h == hops - 1 ? out : ((hops - 1 - h) % 2 ? a : b);
+        ZI_TRY(spmm_f32(g->sys->row_ptr, g->sys->col, g->ahat, src, dst, n, fi, s));
+        src = dst;
+    }
+    return ZI_OK;
+}
+
 zi_status forward(zi_gnn *g, const float *X, hipStream_t s) {
     const int32_t n = g->sys->n;
     ZI_HIP(hipMemcpyAsync(g->H[0], X, sizeof(float) * (size_t)n * g->dims[0],
                           hipMemcpyDeviceToDevice, s));
     for (int k = 0; k < g->K; ++k) {
         const int fi = g->dims[k], fo = g->dims[k + 1];
-        ZI_TRY(spmm_f32(g->sys->row_ptr, g->sys->col, g->ahat, g->H[k], g->M[k], n, fi, s));
+        ZI_TRY(aggregate(g, g->H[k], g->hops[k], fi, g->M[k], g->tmp, g->tmp2, s));
         ZI_TRY(dense(g->H[k], g->params + g->off_ws[k], g->M[k], g->params + g->off_wn[k],
                      g->params + g->off_b[k], nullptr, fi, fo, false, k < g->K - 1, n,
                      g->H[k + 1], s));
@@ -235,7 +250,8 @@ zi_status forward(zi_gnn *g, const float *X, hipStream_t s) {
 
 }  // namespace
 
-zi_status zi_gnn_create_impl(const zi_system *sys, int32_t K, const int32_t *dims, zi_gnn **out) {
+zi_status zi_gnn_create_impl(const zi_system *sys, int32_t K, const int32_t *dims,
+                             const int32_t *hops, zi_gnn **out) {
     zi_gnn *g = new zi_gnn();
     struct Guard {
         zi_gnn *p;
@@ -246,6 +262,8 @@ zi_status zi_gnn_create_impl(const zi_system *sys, int32_t K, const int32_t *dim
     g->sys = sys;
     g->K = K;
     g->dims.assign(dims, dims + K + 1);
+    g->hops.assign(K, 1);
+    if (hops) g->hops.assign(hops, hops + K);
     int64_t off = 0;
     for (int k = 0; k < K; ++k) {
         const int64_t w = (int64_t)dims[k] * dims[k + 1];
@@ -273,6 +291,7 @@ zi_status zi_gnn_create_impl(const zi_system *sys, int32_t K, const int32_t *dim
     ZI_TRY(g->pool.alloc(&g->dZ, (size_t)n * fmax));
     ZI_TRY(g->pool.alloc(&g->dM, (size_t)n * fmax));
     ZI_TRY(g->pool.alloc(&g->tmp, (size_t)n * fmax));
+    ZI_TRY(g->pool.alloc(&g->tmp2, (size_t)n * fmax));
     g->nblk = WG_BLOCKS;
     ZI_TRY(g->pool.alloc(&g->part, (size_t)g->nblk * fmax * fmax));
     ZI_TRY(g->pool.alloc(&g->lpart, (size_t)2 * 1024));
@@ -346,7 +365,7 @@ zi_status zi_gnn_loss_grad_impl(zi_gnn *g, const float *X, const float *t, doubl
         // dM = dZ Wn^T;  dH = dZ Ws^T + Ahat dM
         ZI_TRY(dense(g->dZ, g->params + g->off_wn[k], nullptr, nullptr, nullptr, nullptr, fok, fi,
                      true, false, n, g->dM, s));
-        ZI_TRY(spmm_f32(g->sys->row_ptr, g->sys->col, g->ahat, g->dM, g->tmp, n, fi, s));
+        ZI_TRY(aggregate(g, g->dM, g->hops[k], fi, g->tmp, g->dH, g->tmp2, s));
         ZI_TRY(dense(g->dZ, g->params + g->off_ws[k], nullptr, nullptr, nullptr, g->tmp, fok, fi,
                      true, false, n, g->dH, s));
     }
@@ -366,6 +385,205 @@ zi_status zi_gnn_adam_step_impl(zi_gnn *g, float lr, hipStream_t s) {
     const float c1 = 1.f - powf(b1, (float)g->adam_t), c2 = 1.f - powf(b2, (float)g->adam_t);
     hipLaunchKernelGGL(k_adam, dim3(grid_for(g->nparam, 256)), dim3(256), 0, s, g->params, g->grads,
                        g->adam_m, g->adam_v, g->nparam, lr, b1, b2, 1e-8f, c1, c2);
+    ZI_HIP(hipGetLastError());
+    ZI_HIP(hipStreamSynchronize(s));
+    return ZI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Input features of the warm-start network (see zi_gnn_features in zi.h).
+
+namespace {
+
+constexpr int FEAT = 10;
+constexpr int FBLK = 256;
+constexpr int FBLOCKS = 512;
+
+// raw[3 i + (0, 1, 2)] = (b_il, t0_il, (b_l - A t0_l)_i) and block maxima of
+// |b|, |t0|, |r| and a0_ii (maxima: the same in any order).
+__global__ __launch_bounds__(FBLK) void k_feat_raw(
+    int32_t n, int32_t l, const int32_t *bp, const int32_t *bc, const double *bv,
+    const double *T0, int32_t ldt, const int32_t *rp, const int32_t *ci, const double *va,
+    const double *d0, double *raw, double *part) {
+    __shared__ double sm[4][FBLK];
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * FBLK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * FBLK) {
+        double b = 0.0;
+        for (int32_t k = bp[i]; k < bp[i + 1]; ++k)
+            if (bc[k] == l) b += bv[k];
+        const double t0 = T0[i * ldt + l];
+        double at = 0.0;
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) at = fma(va[q], T0[(int64_t)ci[q] * ldt + l], at);
+        const double r = b - at;
+        raw[3 * i] = b;
+        raw[3 * i + 1] = t0;
+        raw[3 * i + 2] = r;
+        m[0] = fmax(m[0], fabs(b));
+        m[1] = fmax(m[1], fabs(t0));
+        m[2] = fmax(m[2], fabs(r));
+        m[3] = fmax(m[3], d0[i]);
+    }
+    for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] = m[q];
+    __syncthreads();
+    for (int off = FBLK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int q = 0; q < 4; ++q)
+                sm[q][threadIdx.x] = fmax(sm[q][threadIdx.x], sm[q][threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+__global__ void k_feat_max(const double *part, int nblk, double *mx) {
+    const int q = threadIdx.x;
+    if (q >= 4) return;
+    double m = 0.0;
+    for (int b = 0; b < nblk; ++b) m = fmax(m, part[4 * b + q]);
+    mx[q] = m > 0.0 ? m : 1.0;
+}
+
+__global__ void k_feat_write(int32_t n, const double *raw, const double *mx, const double *d,
+                             const double *d0, const double *nodes, double cx, double cy,
+                             double cz, double inv_r, float *X) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = nodes[3 * i], y = nodes[3 * i + 1], z = nodes[3 * i + 2];
+    const double dx = x - cx, dy = y - cy, dz = z - cz;
+    float *o = X + i * FEAT;
+    o[0] = (float)(raw[3 * i] / mx[0]);
+    o[1] = (float)log(d[i] / d0[i]);
+    o[2] = (float)(raw[3 * i + 1] / mx[1]);
+    o[3] = (float)(x * inv_r);
+    o[4] = (float)(y * inv_r);
+    o[5] = (float)(z * inv_r);
+    o[6] = (float)(sqrt(dx * dx + dy * dy + dz * dz) * inv_r);
+    o[7] = (float)log(d0[i] / mx[3]);
+    o[8] = (float)(raw[3 * i + 2] / mx[2]);
+    o[9] = 1.f;   // a constant input (the aggregation sees the node degree)
+}
+
+}  // namespace
+
+zi_status zi_gnn_features_impl(const zi_system *base, const zi_system *pert, const double *T0,
+                               int32_t ldt, int32_t l, const double *centre, double radius,
+                               float *X, hipStream_t s) {
+    const int32_t n = base->n;
+    Pool tmp;
+    double *raw = nullptr, *part = nullptr, *mx = nullptr;
+    ZI_TRY(tmp.alloc(&raw, (size_t)3 * n));
+    ZI_TRY(tmp.alloc(&part, (size_t)4 * FBLOCKS));
+    ZI_TRY(tmp.alloc(&mx, 4));
+    hipLaunchKernelGGL(k_feat_raw, dim3(FBLOCKS), dim3(FBLK), 0, s, n, l, base->b_ptr,
+                       base->b_col, base->b_val, T0, ldt, pert->row_ptr, pert->col, pert->val,
+                       base->diag, raw, part);
+    hipLaunchKernelGGL(k_feat_max, dim3(1), dim3(64), 0, s, part, FBLOCKS, mx);
+    hipLaunchKernelGGL(k_feat_write, dim3(grid_for(n, 256)), dim3(256), 0, s, n, raw, mx,
+                       pert->diag, base->diag, base->nodes, centre[0], centre[1], centre[2],
+                       1.0 / radius, X);
+    ZI_HIP(hipGetLastError());
+    ZI_HIP(hipStreamSynchronize(s));
+    return ZI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Training targets and proposed initial iterates: with s_l = max_i |t0_il|,
+// target t_i = gain (T_i,col - t0_il) / s_l and x0_i = t0_il + s_l y_i / gain.
+
+namespace {
+
+__global__ __launch_bounds__(FBLK) void k_colmax_part(const double *T0, int32_t ldt, int32_t l,
+                                                      int32_t n, double *part) {
+    __shared__ double sm[FBLK];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * FBLK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * FBLK)
+        m = fmax(m, fabs(T0[i * ldt + l]));
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = FBLK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_colmax_final(const double *part, int nblk, double *mx) {
+    if (threadIdx.x != 0) return;
+    double m = 0.0;
+    for (int b = 0; b < nblk; ++b) m = fmax(m, part[b]);
+    mx[0] = m > 0.0 ? m : 1.0;
+}
+
+// target and its sum of squares per block (float64, fixed order)
+__global__ __launch_bounds__(FBLK) void k_target(const double *T, int32_t ldT, int32_t col,
+                                                 const double *T0, int32_t ldt, int32_t l,
+                                                 double gain, const double *mx, int32_t n,
+                                                 float *t, double *part) {
+    __shared__ double sm[FBLK];
+    double a = 0.0;
+    const double f = gain / mx[0];
+    for (int64_t i = (int64_t)blockIdx.x * FBLK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * FBLK) {
+        const float v = (float)(f * (T[i * ldT + col] - T0[i * ldt + l]));
+        t[i] = v;
+        a += (double)v * (double)v;
+    }
+    sm[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = FBLK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sm[threadIdx.x] += sm[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_x0(const float *y, const double *T0, int32_t ldt, int32_t l, double gain,
+                     const double *mx, int32_t n, double *x0, int32_t ldx, int32_t xcol) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    x0[i * ldx + xcol] = T0[i * ldt + l] + mx[0] * (double)y[i] / gain;
+}
+
+zi_status colmax(const double *T0, int32_t ldt, int32_t l, int32_t n, double *part, double *mx,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_colmax_part, dim3(FBLOCKS), dim3(FBLK), 0, s, T0, ldt, l, n, part);
+    hipLaunchKernelGGL(k_colmax_final, dim3(1), dim3(64), 0, s, part, FBLOCKS, mx);
+    ZI_HIP(hipGetLastError());
+    return ZI_OK;
+}
+
+}  // namespace
+
+zi_status zi_gnn_target_impl(const double *T, int32_t ldT, int32_t col, const double *T0,
+                             int32_t ldt, int32_t l, double gain, int32_t n, float *t,
+                             double *sumsq, hipStream_t s) {
+    Pool tmp;
+    double *part = nullptr, *mx = nullptr;
+    ZI_TRY(tmp.alloc(&part, (size_t)FBLOCKS));
+    ZI_TRY(tmp.alloc(&mx, 1));
+    ZI_TRY(colmax(T0, ldt, l, n, part, mx, s));
+    hipLaunchKernelGGL(k_target, dim3(FBLOCKS), dim3(FBLK), 0, s, T, ldT, col, T0, ldt, l, gain,
+                       mx, n, t, part);
+    ZI_HIP(hipGetLastError());
+    std::vector<double> h(FBLOCKS);
+    ZI_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * FBLOCKS, hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipStreamSynchronize(s));
+    double a = 0.0;
+    for (double v : h) a += v;
+    if (sumsq) *sumsq = a;
+    return ZI_OK;
+}
+
+zi_status zi_gnn_x0_impl(const float *y, const double *T0, int32_t ldt, int32_t l, double gain,
+                         int32_t n, double *x0, int32_t ldx, int32_t xcol, hipStream_t s) {
+    Pool tmp;
+    double *part = nullptr, *mx = nullptr;
+    ZI_TRY(tmp.alloc(&part, (size_t)FBLOCKS));
+    ZI_TRY(tmp.alloc(&mx, 1));
+    ZI_TRY(colmax(T0, ldt, l, n, part, mx, s));
+    hipLaunchKernelGGL(k_x0, dim3(grid_for(n, 256)), dim3(256), 0, s, y, T0, ldt, l, gain, mx, n,
+                       x0, ldx, xcol);
     ZI_HIP(hipGetLastError());
     ZI_HIP(hipStreamSynchronize(s));
     return ZI_OK;

@@ -222,7 +222,7 @@ zi_status zi_eit_source(const zi_system *sys, const double *T, int32_t n_pattern
 }
 
 zi_status zi_gnn_create(const zi_system *sys, int32_t n_layers, const int32_t *dims,
-                        zi_gnn **out) {
+                        const int32_t *hops, zi_gnn **out) {
     zi::g_err[0] = 0;
     if (!sys || !dims || !out || n_layers < 1 || n_layers > 32) {
         set_error("null argument or n_layers outside [1, 32]");
@@ -235,7 +235,60 @@ zi_status zi_gnn_create(const zi_system *sys, int32_t n_layers, const int32_t *d
             return ZI_EINVAL;
         }
     }
-    ZI_GUARD(return zi_gnn_create_impl(sys, n_layers, dims, out);)
+    for (int k = 0; hops && k < n_layers; ++k) {
+        if (hops[k] < 1 || hops[k] > 1024) {
+            set_error("hops[%d] = %d: need 1..1024", k, hops[k]);
+            return ZI_EINVAL;
+        }
+    }
+    ZI_GUARD(return zi_gnn_create_impl(sys, n_layers, dims, hops, out);)
+}
+
+zi_status zi_gnn_target(const double *T, int32_t ldT, int32_t col, const double *T0,
+                        int32_t ldt, int32_t electrode, double gain, int32_t n_nodes, float *t,
+                        double *sumsq, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!T || !T0 || !t || n_nodes < 1 || col < 0 || col >= ldT || electrode < 0 ||
+        electrode >= ldt || !(gain > 0.0)) {
+        set_error("null argument, column out of range or gain <= 0");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_gnn_target_impl(T, ldT, col, T0, ldt, electrode, gain, n_nodes, t, sumsq,
+                                       (hipStream_t)hip_stream);)
+}
+
+zi_status zi_gnn_x0(const float *y, const double *T0, int32_t ldt, int32_t electrode,
+                    double gain, int32_t n_nodes, double *x0, int32_t ldx, int32_t xcol,
+                    void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!y || !T0 || !x0 || n_nodes < 1 || electrode < 0 || electrode >= ldt || xcol < 0 ||
+        xcol >= ldx || !(gain > 0.0)) {
+        set_error("null argument, column out of range or gain <= 0");
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_gnn_x0_impl(y, T0, ldt, electrode, gain, n_nodes, x0, ldx, xcol,
+                                   (hipStream_t)hip_stream);)
+}
+
+zi_status zi_gnn_features(const zi_system *base, const zi_system *perturbed, const double *T0,
+                          int32_t ldt, int32_t electrode, const double *centre, double radius,
+                          float *X, void *hip_stream) {
+    zi::g_err[0] = 0;
+    if (!base || !perturbed || !T0 || !centre || !X) {
+        set_error("null argument");
+        return ZI_EINVAL;
+    }
+    if (perturbed->n != base->n || perturbed->nnz != base->nnz) {
+        set_error("the perturbed system must share the base system's mesh");
+        return ZI_EINVAL;
+    }
+    if (electrode < 0 || electrode >= base->L || ldt < base->L || !(radius > 0.0)) {
+        set_error("electrode %d outside [0, %d), ldt %d < L, or radius <= 0", electrode, base->L,
+                  ldt);
+        return ZI_EINVAL;
+    }
+    ZI_GUARD(return zi_gnn_features_impl(base, perturbed, T0, ldt, electrode, centre, radius, X,
+                                         (hipStream_t)hip_stream);)
 }
 
 int64_t zi_gnn_param_count(const zi_gnn *net) { return net ? zi_gnn_param_count_impl(net) : 0; }

@@ -228,7 +228,16 @@ zi_status zi_eit_source_impl(const zi_system *sys, const double *T, int32_t P, c
                              int32_t ne, const int32_t *elems, int32_t *cp, int32_t *ri,
                              double *gv, double *y_bg, hipStream_t s);
 void zi_solver_ws_destroy(zi_solver_ws *ws);
-zi_status zi_gnn_create_impl(const zi_system *sys, int32_t K, const int32_t *dims, zi_gnn **out);
+zi_status zi_gnn_create_impl(const zi_system *sys, int32_t K, const int32_t *dims,
+                             const int32_t *hops, zi_gnn **out);
+zi_status zi_gnn_features_impl(const zi_system *base, const zi_system *pert, const double *T0,
+                               int32_t ldt, int32_t l, const double *centre, double radius,
+                               float *X, hipStream_t s);
+zi_status zi_gnn_target_impl(const double *T, int32_t ldT, int32_t col, const double *T0,
+                             int32_t ldt, int32_t l, double gain, int32_t n, float *t,
+                             double *sumsq, hipStream_t s);
+zi_status zi_gnn_x0_impl(const float *y, const double *T0, int32_t ldt, int32_t l, double gain,
+                         int32_t n, double *x0, int32_t ldx, int32_t xcol, hipStream_t s);
 void zi_gnn_destroy_impl(zi_gnn *g);
 int64_t zi_gnn_param_count_impl(const zi_gnn *g);
 zi_status zi_gnn_set_params_impl(zi_gnn *g, const float *p);

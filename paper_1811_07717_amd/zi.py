@@ -98,8 +98,19 @@ SIGNATURES = [
                                      ctypes.c_void_p, ctypes.c_void_p, c_f64p, ctypes.c_void_p]),
     ("zi_spmm", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_int32, c_f64p, ctypes.c_void_p]),
-    ("zi_gnn_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, c_i32p,
+    ("zi_gnn_create", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, c_i32p, c_i32p,
                                      ctypes.POINTER(ctypes.c_void_p)]),
+    ("zi_gnn_target", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, c_f64p,
+                                     ctypes.c_void_p]),
+    ("zi_gnn_x0", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_void_p]),
+    ("zi_gnn_features", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.c_int32, c_f64p, ctypes.c_double,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
     ("zi_gnn_param_count", ctypes.c_int64, [ctypes.c_void_p]),
     ("zi_gnn_set_params", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("zi_gnn_get_params", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -399,15 +410,58 @@ def transfer_solve_batch(systems, tol=1e-8, maxit=0, precond="jacobi", precision
     return Ts, stats, rc
 
 
+def gnn_features(base, perturbed, T0, electrode, centre, radius, out=None):
+    """zi_gnn_features: the warm-start network's n x 10 float32 input features
+    for electrode column `electrode` of the head `perturbed` (System objects on
+    the same mesh); T0 is the base head's transfer matrix (n x L float64)."""
+    import torch
+    X = out if out is not None else torch.empty((base.n, 10), dtype=torch.float32, device="cuda")
+    c = np.ascontiguousarray(np.asarray(centre, dtype=np.float64).reshape(3))
+    _check(lib().zi_gnn_features(base._h, perturbed._h, _dev(T0, torch.float64, "T0"),
+                                 int(T0.shape[1]), int(electrode), c.ctypes.data_as(c_f64p),
+                                 float(radius), _dev(X, torch.float32, "X"), _stream()),
+           "zi_gnn_features")
+    return X
+
+
+def gnn_target(T, col, T0, electrode, gain=1.0, out=None):
+    """zi_gnn_target: the network's float32 training target for transfer
+    column `col` of T against the base column `electrode` of T0; returns
+    (target, sum of squares)."""
+    import torch
+    n = int(T0.shape[0])
+    t = out if out is not None else torch.empty(n, dtype=torch.float32, device="cuda")
+    ss = ctypes.c_double(0.0)
+    _check(lib().zi_gnn_target(_dev(T, torch.float64, "T"), int(T.shape[1]), int(col),
+                               _dev(T0, torch.float64, "T0"), int(T0.shape[1]), int(electrode),
+                               float(gain), n, _dev(t, torch.float32, "t"), ctypes.byref(ss),
+                               _stream()), "zi_gnn_target")
+    return t, ss.value
+
+
+def gnn_x0(y, T0, electrode, gain, out, col):
+    """zi_gnn_x0: write the proposed initial iterate into column `col` of out
+    (n x k float64) from the network's prediction y (n float32)."""
+    import torch
+    _check(lib().zi_gnn_x0(_dev(y, torch.float32, "y"), _dev(T0, torch.float64, "T0"),
+                           int(T0.shape[1]), int(electrode), float(gain), int(T0.shape[0]),
+                           _dev(out, torch.float64, "x0"), int(out.shape[1]), int(col),
+                           _stream()), "zi_gnn_x0")
+    return out
+
+
 class MeshGNN:
     """zi_gnn: the warm-start mesh-graph network on a system's mesh graph."""
 
-    def __init__(self, system, dims):
+    def __init__(self, system, dims, hops=None):
         self._sys = system
         self.dims = [int(d) for d in dims]
+        self.hops = None if hops is None else [int(h) for h in hops]
         d = np.asarray(self.dims, dtype=np.int32)
+        hp = None if hops is None else np.asarray(self.hops, dtype=np.int32)
         h = ctypes.c_void_p()
         _check(lib().zi_gnn_create(system._h, len(dims) - 1, d.ctypes.data_as(c_i32p),
+                                   None if hp is None else hp.ctypes.data_as(c_i32p),
                                    ctypes.byref(h)), "zi_gnn_create")
         self._h = h
         self.n_params = int(lib().zi_gnn_param_count(self._h))

@@ -46,24 +46,26 @@ def setting():
     g.close()
 
 
-@pytest.mark.parametrize("dims", [[8, 16, 16, 1], [8, 64, 64, 64, 64, 64, 1]])
-def test_forward_loss_gradients_match_oracle(setting, dims):
+@pytest.mark.parametrize("dims,hops", [([8, 16, 16, 1], None),
+                                       ([8, 64, 64, 64, 64, 64, 1], None),
+                                       ([8, 16, 16, 16, 1], [1, 5, 12, 2])])
+def test_forward_loss_gradients_match_oracle(setting, dims, hops):
     from paper_1811_07717_amd import warmstart, zi
     flat = warmstart.glorot_params(dims, seed=3)
-    net = zi.MeshGNN(setting["g"], dims)
+    net = zi.MeshGNN(setting["g"], dims, hops)
     net.set_params(flat)
     Xd = torch.from_numpy(setting["X"]).cuda()
     td = torch.from_numpy(setting["t"]).cuda()
     say(f"[gnn] dims {dims}: {net.n_params} parameters")
     y = net.forward(Xd).cpu().numpy().astype(np.float64)
     params = unflatten(flat, dims)
-    yr, cache = gnn.forward(params, setting["Ah"], setting["X"].astype(np.float64))
+    yr, cache = gnn.forward(params, setting["Ah"], setting["X"].astype(np.float64), hops)
     assert np.abs(y - yr).max() <= 1e-4 * np.abs(yr).max()
     loss, grads = net.loss_grad(Xd, td, want_grads=True)
     tr = setting["t"].astype(np.float64)
     lr_ = gnn.loss(yr, tr)
     assert loss == pytest.approx(lr_, rel=1e-4)
-    gr = flatten(gnn.backward(params, setting["Ah"], cache, yr, tr))
+    gr = flatten(gnn.backward(params, setting["Ah"], cache, yr, tr, hops))
     o = 0
     for k, (fi, fo) in enumerate(zip(dims[:-1], dims[1:])):
         for size in (fi * fo, fi * fo, fo):
@@ -74,9 +76,53 @@ def test_forward_loss_gradients_match_oracle(setting, dims):
     # one Adam step against the oracle's
     net.adam_step(1e-3)
     state = {}
-    gnn.adam_step(params, gnn.backward(params, setting["Ah"], cache, yr, tr), state, lr=1e-3)
+    gnn.adam_step(params, gnn.backward(params, setting["Ah"], cache, yr, tr, hops), state,
+                  lr=1e-3)
     np.testing.assert_allclose(net.get_params(), flatten(params), rtol=1e-4, atol=2e-6)
     net.close()
+
+
+def test_features_targets_and_x0_match_numpy():
+    # zi_gnn_features / zi_gnn_target / zi_gnn_x0 against the same quantities
+    # formed in NumPy from the oracle's matrices of the base and perturbed head
+    from paper_1811_07717_amd import zi
+    H = hm.make_head(8.0, L=10, m=1, seed=4)
+    sig = hm.perturbed_sigma(H, seed=21)
+    base = zi.System.from_head(H)
+    T0, _ = base.transfer_solve(tol=1e-10)
+    k = base._keep
+    pert = zi.System(k[0], k[1], torch.from_numpy(sig).cuda(), k[3], k[4], H.Z)
+    T, _ = pert.transfer_solve(tol=1e-10)
+    S0 = fem.assemble(H.nodes, H.tets, H.sigma, H.tris, H.tri_electrode, H.Z)
+    S1 = fem.assemble(H.nodes, H.tets, sig, H.tris, H.tri_electrode, H.Z)
+    t0 = T0.cpu().numpy()
+    Bd = S0["B"].toarray()
+    R = float(np.linalg.norm(H.nodes, axis=1).max())
+    d0, d1 = S0["A"].diagonal(), S1["A"].diagonal()
+    for l in (0, 7):
+        X = zi.gnn_features(base, pert, T0, l, H.centres[l], R).cpu().numpy()
+        r = Bd[:, l] - S1["A"] @ t0[:, l]
+        ref = np.column_stack([
+            Bd[:, l] / np.abs(Bd[:, l]).max(), np.log(d1 / d0), t0[:, l] / np.abs(t0[:, l]).max(),
+            H.nodes / R, np.linalg.norm(H.nodes - H.centres[l], axis=1) / R,
+            np.log(d0 / d0.max()), r / np.abs(r).max(), np.ones(H.n)])
+        err = np.abs(X - ref).max(axis=0) / np.maximum(np.abs(ref).max(axis=0), 1e-30)
+        say(f"[gnn] features electrode {l}: max relative error per feature {np.round(err, 9)}")
+        assert err.max() <= 1e-6
+        s_l = np.abs(t0[:, l]).max()
+        tt, ss = zi.gnn_target(T, l, T0, l, gain=3.0)
+        want = 3.0 * (T.cpu().numpy()[:, l] - t0[:, l]) / s_l
+        np.testing.assert_allclose(tt.cpu().numpy(), want, rtol=1e-6, atol=1e-7 * np.abs(want).max())
+        assert ss == pytest.approx(float((tt.cpu().numpy().astype(np.float64) ** 2).sum()),
+                                   rel=1e-12)
+        y = torch.linspace(-1, 1, H.n, dtype=torch.float32, device="cuda")
+        x0 = torch.zeros((H.n, 2), dtype=torch.float64, device="cuda")
+        zi.gnn_x0(y, T0, l, 3.0, x0, 1)
+        want = t0[:, l] + s_l * y.cpu().numpy().astype(np.float64) / 3.0
+        np.testing.assert_allclose(x0[:, 1].cpu().numpy(), want, rtol=1e-12, atol=1e-15)
+        assert not x0[:, 0].any()
+    pert.close()
+    base.close()
 
 
 def test_training_is_deterministic(setting):
@@ -105,7 +151,7 @@ def test_learned_warm_start_reduces_iterations():
     # every solve still reaches the tolerance.
     from paper_1811_07717_amd import warmstart
     H = hm.make_head(8.0, L=16, m=1, seed=9)
-    ws = warmstart.WarmStart(H, dims=(8, 32, 32, 32, 1), seed=1, log=say)
+    ws = warmstart.WarmStart(H, dims=(10, 32, 32, 32, 1), hops=(1, 8, 8, 1), seed=1, log=say)
     data = ws.make_dataset(n_fields=24, per_field=4, seed=7)
     hist = ws.train(data, epochs=6, lr=2e-3)
     assert hist[-1] < hist[0] and hist[-1] < 1.0    # below the x0 = t0 level (loss 1)
