@@ -61,15 +61,17 @@ def parse():
     return p.parse_args()
 
 
-def traffic_for(kernel, workload):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source; else None."""
+def traffic_for(kernel, workload, tile):
+    """HBM bytes per product from the committed counter summary, if it was
+    taken on the current kernel source (and, for the SpMM, the same tile);
+    else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    e = d.get(workload, {}).get(kernel)
+    key = f"{kernel}@{tile}" if kernel.startswith("spmm") else kernel
+    e = d.get(workload, {}).get(key)
     from paper_1811_07717_amd.counters import source_hash
     if not e or e.get("source_hash") != source_hash():
         return None
@@ -386,7 +388,8 @@ def main():
         "config": {"workload": a.workload, "h_mm": H.h_mm, "n_nodes": H.n, "n_tets": H.e,
                    "nnz": int(s0.nnz), "nnz_solver": int(s0.nnz_solver), "electrodes": L, "lf_columns": 3 * H.m,
                    "tol": 1e-8, "precond": a.precond, "precision": a.precision,
-                   "tile": stats[-1]["tile"], "columns_solved": K,
+                   "tile": stats[-1]["tile"], "tile_name": zi.tile_names()[stats[-1]["tile"]],
+                   "columns_solved": K,
                    "leadfield": cols is None},
         "lf_build_s": dt,
         "lf_build_s_median": float(np.median(step_s)),
@@ -404,7 +407,7 @@ def main():
                                "timed_launches": v["launches"]} for k, v in ktot.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                     "traffic": traffic_for(dom, a.workload)},
+                     "traffic": traffic_for(dom, a.workload, zi.tile_names()[stats[-1]["tile"]])},
     }
     rf = out["roofline"]
     if rf["traffic"]:

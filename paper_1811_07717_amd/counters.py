@@ -75,9 +75,14 @@ def summarize(fetch_csv, write_csv, copy_mib, spmm_args=None):
         if k == "copy" or k not in wr:
             continue
         fk, wk = fe[k][0], wr[k][0]
+        # the solver's SpMM runs as several slab launches per product (one
+        # residual update per product): bytes per product = slabs x per launch
+        slabs = 1
+        if k.startswith("spmm") and "update" in fe:
+            slabs = max(1, round(fe[k][1] / fe["update"][1]))
         out[k] = dict(fetch_kib=round(fk, 1), write_kib=round(wk, 1),
-                      bytes_per_launch=int(round((fk * ff + wk * wf) * 1024)),
-                      launches=fe[k][1])
+                      bytes_per_launch=int(round((fk * ff + wk * wf) * 1024 * slabs)),
+                      launches=fe[k][1], slabs=slabs)
     return out, ff, wf
 
 
@@ -93,13 +98,16 @@ def main():
     p.add_argument("--md", help="write a markdown table here")
     p.add_argument("--command", default="", help="command line to record in the table")
     a = p.parse_args()
-    alg, spmm_args = {}, None
+    alg, spmm_args, tuned = {}, None, None
     if a.bench:
         with open(a.bench) as f:
             line = [ln for ln in f.read().splitlines() if ln.startswith("{")][-1]
         b = json.loads(line)
         alg = {k: v["bytes_per_launch"] for k, v in b["solver_kernels"].items()}
-        tuned = (b.get("autotune") or {}).get("tile")
+        tuned = (b.get("autotune") or {}).get("tile") or b.get("config", {}).get("tile_name")
+        if not tuned and isinstance(b.get("config", {}).get("tile"), int):
+            from paper_1811_07717_amd import zi
+            tuned = zi.tile_names()[b["config"]["tile"]]
         m = re.match(r"lpr(\d+)_nv(\d+)_", tuned or "")
         if m:
             spmm_args = f"{m.group(1)}, {m.group(2)}"
@@ -112,19 +120,21 @@ def main():
                 d = json.load(f)
         w = d.setdefault(a.workload, {})
         for k, v in res.items():
-            w[k] = dict(v, source_hash=h, fetch_factor=round(ff, 4), write_factor=round(wf, 4))
+            # the SpMM's traffic depends on its tile: one entry per tile
+            key = f"{k}@{tuned}" if (k.startswith("spmm") and tuned) else k
+            w[key] = dict(v, source_hash=h, fetch_factor=round(ff, 4), write_factor=round(wf, 4))
         with open(a.update, "w") as f:
             json.dump(d, f, indent=1, sort_keys=True)
             f.write("\n")
-    rows = ["| kernel | launches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes/launch "
-            "(calibrated) | algorithmic bytes | ratio |", "|---|---|---|---|---|---|---|"]
+    rows = ["| kernel | dispatches | launches per product | FETCH_SIZE KiB per dispatch | "
+            "WRITE_SIZE KiB per dispatch | HBM bytes per product (calibrated) | "
+            "algorithmic bytes | ratio |", "|---|---|---|---|---|---|---|---|"]
     for k, v in sorted(res.items()):
         ab = alg.get(k)
         ratio = f"{v['bytes_per_launch'] / ab:.3f}" if ab else "-"
-        rows.append(f"| {k} | {v['launches']} | {v['fetch_kib']:.1f} | {v['write_kib']:.1f} | "
-                    f"{v['bytes_per_launch']:,} | {ab:,} | {ratio} |" if ab else
-                    f"| {k} | {v['launches']} | {v['fetch_kib']:.1f} | {v['write_kib']:.1f} | "
-                    f"{v['bytes_per_launch']:,} | - | - |")
+        rows.append(f"| {k} | {v['launches']} | {v['slabs']} | {v['fetch_kib']:.1f} | "
+                    f"{v['write_kib']:.1f} | {v['bytes_per_launch']:,} | "
+                    + (f"{ab:,} | {ratio} |" if ab else "- | - |"))
     text = "\n".join(rows) + (f"\n\nCalibration on k_copy2 ({a.copy_mib:g} MiB read + written per "
                               f"launch): FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f}. "
                               f"Kernel source hash {h}.\n")

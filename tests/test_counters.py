@@ -21,13 +21,21 @@ def test_calibration_and_traffic_file(tmp_path):
     upd = "void (anonymous namespace)::k_update<32, 2, double>(Geom, ...)"
     copy = "zi::(anonymous namespace)::k_copy2(double2 const*, double2*, unsigned long)"
     # the copy moves 1 MiB each way; FETCH counts half of it, WRITE all of it
-    _write(tmp_path / "f.csv", [(copy, 512.0), (spmm, 100.0), (spmm, 300.0), (upd, 50.0)])
-    _write(tmp_path / "w.csv", [(copy, 1024.0), (spmm, 10.0), (spmm, 30.0), (upd, 5.0)])
+    _write(tmp_path / "f.csv", [(copy, 512.0), (spmm, 100.0), (spmm, 300.0), (upd, 50.0),
+                                (upd, 50.0)])
+    _write(tmp_path / "w.csv", [(copy, 1024.0), (spmm, 10.0), (spmm, 30.0), (upd, 5.0),
+                                (upd, 5.0)])
     res, ff, wf = counters.summarize(tmp_path / "f.csv", tmp_path / "w.csv", copy_mib=1.0)
     assert ff == 2.0 and wf == 1.0
-    assert res["spmm_pq"]["launches"] == 2
+    assert res["spmm_pq"]["launches"] == 2 and res["spmm_pq"]["slabs"] == 1
     assert res["spmm_pq"]["bytes_per_launch"] == int((200.0 * 2 + 20.0) * 1024)
     assert res["update"]["bytes_per_launch"] == int((50.0 * 2 + 5.0) * 1024)
+    # an SpMM run as two slab launches per product (one update per product)
+    _write(tmp_path / "f2.csv", [(copy, 512.0), (spmm, 100.0), (spmm, 300.0), (upd, 50.0)])
+    _write(tmp_path / "w2.csv", [(copy, 1024.0), (spmm, 10.0), (spmm, 30.0), (upd, 5.0)])
+    res, _, _ = counters.summarize(tmp_path / "f2.csv", tmp_path / "w2.csv", copy_mib=1.0)
+    assert res["spmm_pq"]["slabs"] == 2
+    assert res["spmm_pq"]["bytes_per_launch"] == 2 * int((200.0 * 2 + 20.0) * 1024)
     assert "copy" not in res
 
 
