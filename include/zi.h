@@ -121,7 +121,10 @@ typedef struct {
                             (the SpMM and updates of every 8th
                             iteration, and every full flush) */
     int32_t tile;        /* SpMM tile id (see zi_tile_count); -1 -> the tile
-                            zi_autotune chose, else a width-based default */
+                            zi_autotune chose, else a width-based default.
+                            The LDS ring tile serves the single-reduction
+                            FP64 form only; other forms reject it
+                            (ZI_EINVAL) */
     int32_t graph;       /* 1: replay the iteration loop as a hipGraph of
                             check_every iterations (no per-kernel timing) */
     const double *x0;    /* n_nodes x L initial iterate, or NULL for zero */
@@ -193,16 +196,17 @@ zi_status zi_transfer_solve_batch(zi_system *const *systems, int32_t n_systems,
                                   const zi_solve_opts *opts, double *const *T,
                                   zi_solve_stats *stats, void *hip_stream);
 
-/* Autotuner: scores every tile by one PCG iteration's kernels on this
+/* Autotuner: scores every tile by the SpMM of one PCG iteration on this
  * system's n x L block in the given precision and stores the best; later
- * solves with tile = -1 use it.  ZI_FP64 times the single-reduction kernels
- * (SpMM S = A D^-1 R + beta S and the residual update; the lazy P and X
- * flush has a fixed geometry), ZI_FP32_SPMM_IR the classic ones (SpMM
- * Q = A P, residual update, direction update, 1/8 of the X flush); each
- * kernel the best of three launches after a warm-up.  The workspace's
- * contents are overwritten.  best_tile (HOST, may be NULL) receives the
- * choice; ms (HOST, may be NULL, zi_tile_count() entries) the per-iteration
- * milliseconds per tile. */
+ * solves with tile = -1 use it.  ZI_FP64 times the single-reduction SpMM
+ * S = A D^-1 R + beta S, ZI_FP32_SPMM_IR the classic SpMM Q = A P with
+ * float32 vectors; the residual and direction updates and the flushes run
+ * with one fixed geometry whatever the tile, and no tile changes a result
+ * bit.  Each tile: the best of three launches after a warm-up.  The
+ * workspace's contents are overwritten.  best_tile (HOST, may be NULL)
+ * receives the choice; ms (HOST, may be NULL, zi_tile_count() entries) the
+ * milliseconds per tile, -1 for a tile that the precision cannot use (the
+ * LDS ring tile in ZI_FP32_SPMM_IR). */
 zi_status zi_autotune(zi_system *sys, int32_t precision, int32_t *best_tile, double *ms,
                       void *hip_stream);
 
@@ -277,8 +281,8 @@ zi_status zi_eit_source(const zi_system *sys, const double *T, int32_t n_pattern
 /* Y = A X for the assembled (grounded) A; X and Y are n_nodes x k row-major,
  * k even.  The product the PCG iterates (the solver's copy of A, see
  * zi_system_info.nnz_solver); exposed for tests and bandwidth measurement.
- * tile as in zi_solve_opts.  ms_out (HOST, may be NULL) receives the
- * event-timed kernel duration. */
+ * tile as in zi_solve_opts, except the LDS ring tile (ZI_EINVAL).  ms_out
+ * (HOST, may be NULL) receives the event-timed kernel duration. */
 zi_status zi_spmm(const zi_system *sys, int32_t k, const double *X, double *Y,
                   int32_t tile, double *ms_out, void *hip_stream);
 
@@ -350,7 +354,10 @@ zi_status zi_gnn_x0(const float *y, const double *T0, int32_t ldt, int32_t elect
  * Used as the plain copy of known size that calibrates HBM counters. */
 zi_status zi_copy_probe(const double *src, double *dst, int64_t n, double *ms, void *hip_stream);
 
-/* Number of SpMM tile configurations and a description of tile t. */
+/* Number of SpMM tile configurations and a description of tile t:
+ * lpr<lanes per row>_nv<column pairs per lane>_cw<chunk width>, with _front
+ * for the cooperative-front schedule, or ring_g<rows per step>_cw<chunk
+ * width> for the LDS ring SpMM of the single-reduction form. */
 int32_t zi_tile_count(void);
 const char *zi_tile_name(int32_t t);
 

@@ -29,7 +29,7 @@ KERNEL_SOURCES = ["paper_1811_07717_amd/csrc/k_pcg.hip",
 
 # rocprofv3 kernel name -> solver kernel key used by bench.py
 KERNELS = [(re.compile(r"k_spmm<.*, true>"), "spmm_pq"),
-           (re.compile(r"k_spmm_sr<"), "spmm_sr"),
+           (re.compile(r"k_spmm_sr(<|_ring)"), "spmm_sr"),
            (re.compile(r"k_update<"), "update"),
            (re.compile(r"k_pupdate<"), "pupdate"),
            (re.compile(r"k_xflush<"), "xflush"),
@@ -57,7 +57,8 @@ def per_kernel(path, spmm_args=None):
             for pat, key in KERNELS:
                 if pat.search(name):
                     if (spmm_args and key.startswith("spmm")
-                            and f"<{spmm_args}" not in name):
+                            and (f"<{spmm_args}" if spmm_args != "ring" else "_ring(")
+                            not in name):
                         break
                     vals[key].append(float(r["Counter_Value"]))
                     break
@@ -111,6 +112,8 @@ def main():
         m = re.match(r"lpr(\d+)_nv(\d+)_", tuned or "")
         if m:
             spmm_args = f"{m.group(1)}, {m.group(2)}"
+        elif (tuned or "").startswith("ring"):
+            spmm_args = "ring"
     res, ff, wf = summarize(a.fetch, a.write, a.copy_mib, spmm_args)
     h = source_hash()
     if a.update:

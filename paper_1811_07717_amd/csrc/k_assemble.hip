@@ -490,12 +490,13 @@ __device__ __forceinline__ bool keep_entry(int64_t i, int32_t j, double v, const
 // grid plane apart, far more rows than one XCD's L2 holds, so each row of the
 // block is fetched from memory about three times per product.  The solver
 // therefore renumbers the nodes: the bounding box is cut into cubic cells of
-// about one node spacing, the cells into pencils of PENCIL x PENCIL cells
-// along z, the pencils are visited in a snake order (and z alternates
-// direction from pencil to pencil), and inside a pencil the nodes go by z,
-// then y, then x.  Mesh neighbours are then at most a pencil layer (a few
-// hundred rows) apart.  Nodes sharing a cell keep their relative order, so
-// the permutation is deterministic.
+// the mesh's volume per node (so that a cell holds about one node), the cells
+// into pencils of PENCIL x PENCIL cells along z, the pencils are visited in a
+// snake order (and z alternates direction from pencil to pencil), and inside
+// a pencil the nodes go by z, then y, then x.  Mesh neighbours are then at
+// most a pencil layer (about PENCIL^2 rows) apart, except across the side
+// faces of a pencil.  Nodes sharing a cell keep their relative order, so the
+// permutation is deterministic.
 constexpr int PENCIL = 8;
 
 struct CellGrid {
@@ -529,6 +530,25 @@ __global__ void k_bbox_part(const double *nodes, int32_t n, double *part) {
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
+// Per-block sums of the tet volumes |det J| / 6 (fixed-order tree reduction).
+__global__ void k_volume_part(const double *nodes, const int32_t *tets, int32_t e, double *part) {
+    __shared__ double s[256];
+    double v = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < e;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const V3 x0 = load3(nodes, tets[4 * t]), x1 = load3(nodes, tets[4 * t + 1]);
+        const V3 x2 = load3(nodes, tets[4 * t + 2]), x3 = load3(nodes, tets[4 * t + 3]);
+        v += fabs(dot(sub(x1, x0), cross(sub(x2, x0), sub(x3, x0)))) / 6.0;
+    }
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
 __device__ __forceinline__ int cell_of(double x, double lo, double h, int nc) {
     const double t = (x - lo) / h;
     if (!(t > 0.0)) return 0;
@@ -552,10 +572,12 @@ __global__ void k_inverse_perm(const int32_t *perm, int32_t n, int32_t *iperm) {
     if (r < n) iperm[perm[r]] = (int32_t)r;
 }
 
-// Cell grid for n nodes in the box [lo, hi]: cells of the edge length that
-// gives about one node per cell of the box, enlarged where the key space
-// would exceed 4 n + 4096 buckets (flat or strongly graded meshes).
-CellGrid make_cell_grid(const double lo[3], const double hi[3], int32_t n, int64_t *buckets) {
+// Cell grid for n nodes in the box [lo, hi] of a mesh of volume vol: cells of
+// the volume per node (of the box's, where vol is not positive), enlarged
+// where the key space would exceed 4 n + 4096 buckets (flat or strongly
+// graded meshes).
+CellGrid make_cell_grid(const double lo[3], const double hi[3], int32_t n, double vol_mesh,
+                        int64_t *buckets) {
     CellGrid g{};
     double ext[3], emax = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -566,6 +588,7 @@ CellGrid make_cell_grid(const double lo[3], const double hi[3], int32_t n, int64
     const double floor_ext = emax > 0.0 ? 1e-6 * emax : 1.0;
     double vol = 1.0;
     for (int k = 0; k < 3; ++k) vol *= std::max(ext[k], floor_ext);
+    if (vol_mesh > 0.0 && std::isfinite(vol_mesh) && vol_mesh < vol) vol = vol_mesh;
     g.h = std::cbrt(vol / std::max(n, 1));
     if (!(g.h > 0.0) || !std::isfinite(g.h)) g.h = 1.0;
     const int64_t cap = 4 * (int64_t)n + 4096;
@@ -942,11 +965,18 @@ zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t
         constexpr int NBB = 256;
         double *bb = nullptr;
         ZI_TRY(tmp.alloc(&bb, (size_t)NBB * 6));
+        double *vb = nullptr;
+        ZI_TRY(tmp.alloc(&vb, (size_t)NBB));
         hipLaunchKernelGGL(k_bbox_part, dim3(NBB), dim3(256), 0, s, sys->nodes, n, bb);
+        hipLaunchKernelGGL(k_volume_part, dim3(NBB), dim3(256), 0, s, sys->nodes, sys->tets, e,
+                           vb);
         ZI_HIP(hipGetLastError());
-        std::vector<double> hb((size_t)NBB * 6);
+        std::vector<double> hb((size_t)NBB * 6), hv((size_t)NBB);
         ZI_HIP(hipMemcpyAsync(hb.data(), bb, sizeof(double) * NBB * 6, hipMemcpyDeviceToHost, s));
+        ZI_HIP(hipMemcpyAsync(hv.data(), vb, sizeof(double) * NBB, hipMemcpyDeviceToHost, s));
         ZI_HIP(hipStreamSynchronize(s));
+        double vol_mesh = 0.0;
+        for (int b = 0; b < NBB; ++b) vol_mesh += hv[b];
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int b = 0; b < NBB; ++b)
             for (int k = 0; k < 3; ++k) {
@@ -954,7 +984,7 @@ zi_status zi_assemble_impl(const zi_mesh *mesh, const zi_electrodes *el, int32_t
                 hi[k] = std::max(hi[k], hb[b * 6 + 3 + k]);
             }
         int64_t nbk = 0;
-        const CellGrid cg = make_cell_grid(lo, hi, n, &nbk);
+        const CellGrid cg = make_cell_grid(lo, hi, n, vol_mesh, &nbk);
         int32_t *key = nullptr, *kptr = nullptr;
         ZI_TRY(tmp.alloc(&key, (size_t)n));
         ZI_TRY(tmp.alloc(&kptr, (size_t)nbk + 1));

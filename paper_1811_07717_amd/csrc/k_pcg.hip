@@ -22,6 +22,7 @@
 // fixed order, so results are bitwise reproducible.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -469,6 +470,364 @@ void k_spmm_sr(Geom g, const int32_t *__restrict__ rp,
     });
     double *const parts[2] = {part, part + (size_t)g.nrt * g.ldp};
     block_partials<LPR, NV, 2>(g, ln, sc.cc, sc.prow, dotacc, parts);
+}
+
+// Ring SpMM of the single-reduction PCG: the same products and dot partials
+// as k_spmm_sr, with the gathered rows of R served from LDS.
+//
+// Each block sweeps one contiguous range of solver rows for one 16-column
+// chunk, RING_G rows per step.  The rows [s - RING_H, s + RING_G + RING_H)
+// around step s stay in an LDS ring (in the solver order every mesh
+// neighbour of a row lies within a pencil layer, at most RING_H rows away,
+// except across the pencil's side faces), and the rows that the step's rows
+// reference outside that window -- the side-face neighbours, listed per step
+// by k_ring_halo -- are staged in LDS beside it.  While a step is computed
+// from LDS, the next step's new ring rows, halo rows, matrix entries, S and
+// D^-1 are already on their way into registers; the indices they depend on
+// (row pointers, halo lists) are fetched one step earlier still.  A
+// reference found in neither (a halo list cut at RING_HMAX rows) is gathered
+// from memory.  Each entry of A D^-1 R is formed in CSR order with the same
+// fused multiply-adds as in k_spmm_sr, and delta is summed on the fold
+// grids, so S and the dot products are bitwise those of every other tile.
+constexpr int RING_RPL = 2;                         // rows per lane group per step
+constexpr int RING_HPL = 3;                         // halo rows per lane group per step
+constexpr int RING_G = 32 * RING_RPL;               // rows per step (32 lane groups)
+constexpr int RING_H = 64;                          // window reach below and above a step
+constexpr int RING_ROWS = RING_G + 2 * RING_H;      // rows held in the LDS ring
+constexpr int RING_HMAX = 32 * RING_HPL;            // halo rows staged per step
+constexpr int RING_HSEARCH = 128;                   // halo list in LDS, padded to a power of 2
+constexpr int RING_CW = 16;                         // columns per chunk (8 lanes x double2)
+constexpr int RING_SORT = 1024;                     // halo candidates sorted per step
+static_assert(RING_HMAX <= RING_HSEARCH, "halo search");
+
+// Halo list of every step: the distinct columns, ascending, that rows
+// [s, s + RING_G) reference outside [s - RING_H, s + RING_G + RING_H); the
+// first RING_HMAX of them, the rest of the list INT_MAX.  slow[step] = 1
+// where the list was cut or a row has more than 8 entries: such steps take
+// the ring kernel's path that reads memory inside the row loop.  One block
+// per step.
+__global__ __launch_bounds__(256) void k_ring_halo(const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, int n,
+                                                   int32_t *__restrict__ halo,
+                                                   int32_t *__restrict__ slow) {
+    static_assert(RING_G * 4 <= 256 * 1, "one thread quarter per row");
+    __shared__ int list[RING_SORT];
+    __shared__ int cnt, longrow;
+    const int step = blockIdx.x;
+    const int s0 = step * RING_G;
+    if (threadIdx.x == 0) cnt = longrow = 0;
+    __syncthreads();
+    const int row = s0 + (int)(threadIdx.x >> 2);
+    if (row < n && (int)(threadIdx.x >> 2) < RING_G) {
+        if ((threadIdx.x & 3) == 0 && rp[row + 1] - rp[row] > 8) longrow = 1;
+        const int lo = s0 - RING_H, hi = s0 + RING_G + RING_H;
+        for (int q = rp[row] + (int)(threadIdx.x & 3); q < rp[row + 1]; q += 4) {
+            const int col = ci[q];
+            if (col < lo || col >= hi) {
+                const int p = atomicAdd(&cnt, 1);
+                if (p < RING_SORT) list[p] = col;
+            }
+        }
+    }
+    __syncthreads();
+    const int m = min(cnt, RING_SORT);
+    for (int i = threadIdx.x; i < RING_SORT; i += blockDim.x)
+        if (i >= m) list[i] = INT_MAX;
+    __syncthreads();
+    for (int k = 2; k <= RING_SORT; k <<= 1)        // bitonic sort, ascending
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < RING_SORT; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int x = list[i], y = list[l];
+                    if ((x > y) == ((i & k) == 0)) {
+                        list[i] = y;
+                        list[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    if (threadIdx.x == 0) {
+        int32_t *h = halo + (size_t)step * RING_HMAX;
+        int out = 0, cut = cnt > RING_SORT;
+        for (int i = 0; i < m; ++i)
+            if (i == 0 || list[i] != list[i - 1]) {
+                if (out == RING_HMAX) {
+                    cut = 1;
+                    break;
+                }
+                h[out++] = list[i];
+            }
+        for (; out < RING_HMAX; ++out) h[out] = INT_MAX;
+        slow[step] = cut || longrow;
+    }
+}
+
+// R[row, c..c+1], or 0 where the lane or the row lies outside the block.
+__device__ __forceinline__ double2 ring_row(const double *__restrict__ R, int row, int n, int ldp,
+                                            int c, bool ok) {
+    double2 v = make_double2(0.0, 0.0);
+    if (ok && row >= 0 && row < n) v = ld2(R + (size_t)row * ldp + c);
+    return v;
+}
+
+// X[col, c..c+1] for the ring SpMM at a step whose window starts at lo: from
+// the ring when col lies in the window, else from the staged halo rows
+// (lower bound in the sorted, INT_MAX-padded halo list), else from memory.
+__device__ __forceinline__ double2 ring_fetch(const double2 (*ring)[8], const double2 (*hrow)[8],
+                                              const int *hidx, const double *__restrict__ R,
+                                              int col, int lo, int pr, int n, int ldp, int c,
+                                              bool ok) {
+    if ((unsigned)(col - lo) < (unsigned)RING_ROWS) return ring[col % RING_ROWS][pr];
+    int p = 0;
+#pragma unroll
+    for (int w = RING_HSEARCH / 2; w > 0; w >>= 1)
+        if (hidx[p + w - 1] < col) p += w;
+    if (hidx[p] == col) return hrow[p][pr];
+    return ring_row(R, col, n, ldp, c, ok);
+}
+
+// The same where every reference is known to be in the window or the halo.
+__device__ __forceinline__ double2 ring_fetch_staged(const double2 (*ring)[8],
+                                                     const double2 (*hrow)[8], const int *hidx,
+                                                     int col, int lo, int pr) {
+    if ((unsigned)(col - lo) < (unsigned)RING_ROWS) return ring[col % RING_ROWS][pr];
+    int p = 0;
+#pragma unroll
+    for (int w = RING_HSEARCH / 2; w > 0; w >>= 1)
+        if (hidx[p + w - 1] < col) p += w;
+    return hrow[p][pr];
+}
+
+// The next step's loads of one lane: matrix entry (lane pr of the row's
+// group holds entry pr), S and D^-1 of each of its rows.
+struct RingRows {
+    int ci[RING_RPL];
+    double va[RING_RPL], di[RING_RPL];
+    double2 s[RING_RPL];
+    int rp[RING_RPL][2];
+};
+
+// Block b runs on XCD b mod 8; the ncc chunk blocks of one row range are
+// numbered consecutively on one XCD, so that they run together and share
+// the range's matrix entries (and halo rows) in that XCD's L2.
+__global__ __launch_bounds__(BLOCK) void k_spmm_sr_ring(Geom g, const int32_t *__restrict__ halo,
+                                                        const int32_t *__restrict__ slow,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        const double *__restrict__ vs,
+                                                        const double *__restrict__ dinv,
+                                                        const double *__restrict__ R,
+                                                        const double *__restrict__ beta,
+                                                        double *__restrict__ S, double *part,
+                                                        const double *__restrict__ bound) {
+    static_assert(Lane<8, 1>::RSTEP == 32 && RING_CW == Lane<8, 1>::CW, "ring lanes");
+    static_assert(RING_HMAX * 8 * sizeof(double2) >= 2 * 32 * RING_CW * sizeof(double),
+                  "the halo rows double as the partial-sum buffer");
+    if (g.gate && *g.gate == 0) return;
+    const int bx = blockIdx.x;
+    const int j = bx >> 3;
+    const int cc = j % g.ncc;
+    const int range = (j / g.ncc) * 8 + (bx & 7);
+    if (range >= g.nrt) return;
+    const int a = range * g.rb;                 // a multiple of RING_G
+    const int e = min(g.n, a + g.rb);
+    const int n = g.n, ldp = g.ldp;
+    const Lane<8, 1> ln(g, cc);
+    const int rl = ln.slot, pr = ln.lr;         // lane group (row rl + 32 k of a step), pair
+    const int c = ln.c[0];
+    const bool ok = ln.ok[0];
+
+    __shared__ double2 ring[RING_ROWS][8];
+    __shared__ double2 hrow[RING_HMAX][8];
+    __shared__ int hidx[RING_HSEARCH];
+    __shared__ double m1[RING_CW];              // first fold grid of the chunk's columns
+    const double f2 = ldexp(1.0, g.cl2n - 52);
+    double2 be = make_double2(0.0, 0.0);
+    if (ok && beta) be = ld2(beta + c);
+    const double2 zero = make_double2(0.0, 0.0);
+
+    // loads of step t's entries, S and D^-1 (row pointers already known)
+    auto load_rows = [&](int t, RingRows &q) {
+#pragma unroll
+        for (int k = 0; k < RING_RPL; ++k) {
+            q.ci[k] = 0;
+            q.va[k] = 0.0;
+            q.di[k] = 0.0;
+            q.s[k] = make_double2(0.0, 0.0);
+            const int row = t + rl + 32 * k;
+            if (row < e) {
+                if (pr < q.rp[k][1] - q.rp[k][0]) {
+                    q.ci[k] = ci[q.rp[k][0] + pr];
+                    q.va[k] = vs[q.rp[k][0] + pr];
+                }
+                q.di[k] = dinv[row];
+                if (ok && beta) q.s[k] = ldn2(S + (size_t)row * ldp + c);
+            }
+        }
+    };
+    auto load_rp = [&](int t, int (&r)[RING_RPL][2]) {
+#pragma unroll
+        for (int k = 0; k < RING_RPL; ++k) {
+            const int row = min(t + rl + 32 * k, n);
+            r[k][0] = rp[row];
+            r[k][1] = rp[min(row + 1, n)];
+        }
+    };
+
+    // window and halo of the first step
+    if (threadIdx.x < RING_CW) {
+        const int col = cc * RING_CW + threadIdx.x;
+        m1[threadIdx.x] = col < ldp ? fold_grid(bound[col]) : 0.0;
+    }
+    for (int i = threadIdx.x; i < RING_ROWS * 8; i += BLOCK) {
+        const int row = a - RING_H + (i >> 3);
+        if (row >= 0) {
+            const int col = cc * RING_CW + 2 * (i & 7);
+            double2 v = zero;
+            if (row < n && col < ldp) v = ld2(R + (size_t)row * ldp + col);
+            ring[row % RING_ROWS][i & 7] = v;
+        }
+    }
+    for (int i = threadIdx.x; i < RING_HSEARCH; i += BLOCK)
+        hidx[i] = i < RING_HMAX ? halo[(size_t)(a / RING_G) * RING_HMAX + i] : INT_MAX;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RING_HPL; ++k) {
+        const int h = hidx[rl + 32 * k];
+        hrow[rl + 32 * k][pr] = ring_row(R, h != INT_MAX ? h : -1, n, ldp, c, ok);
+    }
+    RingRows cur, nxt;
+    load_rp(a, cur.rp);
+    load_rp(a + RING_G, nxt.rp);
+    load_rows(a, cur);
+    int hi_n[RING_HPL];                          // halo indices of the next step
+#pragma unroll
+    for (int k = 0; k < RING_HPL; ++k)
+        hi_n[k] = a + RING_G < e ? halo[(size_t)(a / RING_G + 1) * RING_HMAX + rl + 32 * k]
+                                 : INT_MAX;
+    int slow_c = slow[a / RING_G];               // this step's and the next step's path
+    int slow_n = a + RING_G < e ? slow[a / RING_G + 1] : 0;
+    __syncthreads();
+
+    double2 dot0 = zero, dot1 = zero;           // the two fold sums of delta
+    for (int s = a; s < e; s += RING_G) {
+        const int t = s + RING_G;               // the next step
+        const bool has_t = t < e;
+        // next step: new ring rows, halo rows, entries, S, D^-1; the step
+        // after: row pointers and halo indices
+        double2 rn[RING_RPL], hn[RING_HPL];
+        int hi_nn[RING_HPL], rp_nn[RING_RPL][2], slow_nn = 0;
+#pragma unroll
+        for (int k = 0; k < RING_RPL; ++k) {
+            rn[k] = zero;
+            rp_nn[k][0] = rp_nn[k][1] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < RING_HPL; ++k) {
+            hn[k] = zero;
+            hi_nn[k] = INT_MAX;
+        }
+        if (has_t) {
+#pragma unroll
+            for (int k = 0; k < RING_RPL; ++k)
+                rn[k] = ring_row(R, t + RING_H + rl + 32 * k, n, ldp, c, ok);
+#pragma unroll
+            for (int k = 0; k < RING_HPL; ++k)
+                hn[k] = ring_row(R, hi_n[k] != INT_MAX ? hi_n[k] : -1, n, ldp, c, ok);
+            load_rows(t, nxt);
+            const int u = t + RING_G;
+            if (u < e) {
+#pragma unroll
+                for (int k = 0; k < RING_HPL; ++k)
+                    hi_nn[k] = halo[(size_t)(u / RING_G) * RING_HMAX + rl + 32 * k];
+                slow_nn = slow[u / RING_G];
+            }
+            load_rp(u, rp_nn);
+        }
+
+        // this step, from LDS: rows of up to 8 entries whose references are
+        // all staged take the path that reads no memory (the entries and S
+        // came in with the previous step); the others read their entries
+        // and unstaged references inside the row loop
+        const int lo = s - RING_H;
+#pragma unroll
+        for (int k = 0; k < RING_RPL; ++k) {
+            const int row = s + rl + 32 * k;
+            if (row >= e) continue;
+            double2 acc = zero;
+            if (!slow_c) {
+                const int cnt = cur.rp[k][1] - cur.rp[k][0];
+                for (int q = 0; q < cnt; ++q) {
+                    const int col = __shfl(cur.ci[k], q, 8);
+                    const double av = __shfl(cur.va[k], q, 8);
+                    const double2 xv = ring_fetch_staged(ring, hrow, hidx, col, lo, pr);
+                    acc.x = fma(av, xv.x, acc.x);
+                    acc.y = fma(av, xv.y, acc.y);
+                }
+            } else {
+                for (int q = cur.rp[k][0]; q < cur.rp[k][1]; ++q) {
+                    const int col = ci[q];
+                    const double av = vs[q];
+                    const double2 xv = ring_fetch(ring, hrow, hidx, R, col, lo, pr, n, ldp, c, ok);
+                    acc.x = fma(av, xv.x, acc.x);
+                    acc.y = fma(av, xv.y, acc.y);
+                }
+            }
+            if (ok) {
+                double2 sn;
+                sn.x = fma(be.x, cur.s[k].x, acc.x);
+                sn.y = fma(be.y, cur.s[k].y, acc.y);
+                stn2(S + (size_t)row * ldp + c, sn);
+                // the row itself lies in the window
+                const double2 xs = ring[row % RING_ROWS][pr];
+                const int cl = 2 * pr;
+                fold_add(xs.x * cur.di[k], acc.x, m1[cl], f2, dot0.x, dot1.x);
+                fold_add(xs.y * cur.di[k], acc.y, m1[cl + 1], f2, dot0.y, dot1.y);
+            }
+        }
+        __syncthreads();
+        if (has_t) {   // the slots of rows [s - RING_H, s - RING_H + RING_G) are free now
+#pragma unroll
+            for (int k = 0; k < RING_RPL; ++k)
+                ring[(t + RING_H + rl + 32 * k) % RING_ROWS][pr] = rn[k];
+#pragma unroll
+            for (int k = 0; k < RING_HPL; ++k) {
+                hrow[rl + 32 * k][pr] = hn[k];
+                if (pr == 0) hidx[rl + 32 * k] = hi_n[k];
+            }
+        }
+        __syncthreads();
+        cur = nxt;
+        slow_c = slow_n;
+        slow_n = slow_nn;
+#pragma unroll
+        for (int k = 0; k < RING_RPL; ++k) {
+            nxt.rp[k][0] = rp_nn[k][0];
+            nxt.rp[k][1] = rp_nn[k][1];
+        }
+#pragma unroll
+        for (int k = 0; k < RING_HPL; ++k) hi_n[k] = hi_nn[k];
+    }
+
+    // partials of the range, summed over the block's lane groups in a fixed
+    // order (the halo rows serve as the buffer: the loop ended on a barrier)
+    double(*red)[32][RING_CW] = reinterpret_cast<double(*)[32][RING_CW]>(&hrow[0][0]);
+    red[0][rl][2 * pr] = dot0.x;
+    red[0][rl][2 * pr + 1] = dot0.y;
+    red[1][rl][2 * pr] = dot1.x;
+    red[1][rl][2 * pr + 1] = dot1.y;
+    __syncthreads();
+    if (threadIdx.x < 2 * RING_CW) {
+        const int q = threadIdx.x / RING_CW, cl = threadIdx.x % RING_CW;
+        const int col = cc * RING_CW + cl;
+        if (col < ldp) {
+            double sum = 0.0;
+            for (int k = 0; k < 32; ++k) sum += red[q][k][cl];
+            part[(size_t)q * g.nrt * ldp + (size_t)col * g.nrt + range] = sum;
+        }
+    }
 }
 
 // Rows per lane per step in the streaming kernels (measured best on gfx950:
@@ -1027,6 +1386,7 @@ __global__ __launch_bounds__(RED) void k_gate(const int32_t *active, int ldp, co
 struct TileCfg {
     int lpr, nv, front;
     const char *name;
+    int ring = 0;   // 1: the LDS ring SpMM (single-reduction FP64 form only)
 };
 
 constexpr TileCfg kTiles[] = {
@@ -1039,9 +1399,11 @@ constexpr TileCfg kTiles[] = {
     {32, 1, 1, "lpr32_nv1_cw64_front"},  {32, 2, 1, "lpr32_nv2_cw128_front"},
     {16, 1, 1, "lpr16_nv1_cw32_front"},  {16, 2, 1, "lpr16_nv2_cw64_front"},
     {8, 1, 1, "lpr8_nv1_cw16_front"},    {8, 2, 1, "lpr8_nv2_cw32_front"},
+    {8, 1, 0, "ring_g64_cw16", 1},
 };
 constexpr int NTILES = sizeof(kTiles) / sizeof(kTiles[0]);
 static_assert(NTILES <= 32, "residency cache size");
+static_assert(RING_G == 64, "the ring tile's name gives its step");
 
 #define ZI_TILE_SWITCH(tile, FN, ...)                       \
     switch (kTiles[tile].lpr * 8 + kTiles[tile].nv) {       \
@@ -1094,7 +1456,19 @@ Geom make_geom(int n, int ldp, int tile, int resident = 0, int slabs = 1) {
     while ((1ll << g.cl2n) < (long long)n) ++g.cl2n;
     g.ncc = (ldp + cw - 1) / cw;
     g.front = t.front;
-    if (!t.front) {
+    if (t.ring) {
+        // one block per (row range, chunk), as many as the chip holds at once
+        // (at most TARGET_BLOCKS); ranges of whole steps, at least four
+        const int target = std::max(1, (resident > 0 ? std::min(8 * resident, TARGET_BLOCKS)
+                                                      : TARGET_BLOCKS) / g.ncc);
+        int rb = (n + target - 1) / target;
+        rb = std::max(4 * RING_G, ((rb + RING_G - 1) / RING_G) * RING_G);
+        g.rb = rb;
+        g.nrt = (n + rb - 1) / rb;
+        g.nb = g.ncc * g.nrt;
+        g.nb_pad = 8 * g.ncc * ((g.nrt + 7) / 8);
+        g.slabs = 1;
+    } else if (!t.front) {
         int nrt_target = TARGET_BLOCKS / g.ncc;
         if (nrt_target < 1) nrt_target = 1;
         int rb = (n + nrt_target - 1) / nrt_target;
@@ -1158,7 +1532,12 @@ int resident_blocks(GK k, int tile) {
     static int cache[(int)GK::COUNT][32] = {};
     std::lock_guard<std::mutex> lk(mu);
     int &r = cache[(int)k][tile];
-    if (r == 0) ZI_TILE_SWITCH(tile, occupancy_of, k, &r);
+    if (r == 0) {
+        if (kTiles[tile].ring)
+            r = resident_per_xcd(k_spmm_sr_ring);
+        else
+            ZI_TILE_SWITCH(tile, occupancy_of, k, &r);
+    }
     return r;
 }
 
@@ -1209,6 +1588,31 @@ void launch_spmm_sr(const Geom &g, hipStream_t s, const int32_t *rp, const int32
     for (gs.cur = 0; gs.cur < g.slabs; ++gs.cur)
         hipLaunchKernelGGL((k_spmm_sr<LPR, NV>), dim3(g.nb_pad), dim3(BLOCK), 0, s, gs, rp, ci,
                            vs, dinv, R, beta, S, part, bound);
+}
+
+// halo: the system's ring lists (ring_halo), followed by the steps' path flags.
+void launch_spmm_sr_ring(const Geom &g, hipStream_t s, const int32_t *halo, const int32_t *rp,
+                         const int32_t *ci, const double *vs, const double *dinv, const double *R,
+                         const double *beta, double *S, double *part, const double *bound) {
+    const size_t steps = ((size_t)g.n + RING_G - 1) / RING_G;
+    hipLaunchKernelGGL(k_spmm_sr_ring, dim3(g.nb_pad), dim3(BLOCK), 0, s, g, halo,
+                       halo + steps * RING_HMAX, rp, ci, vs, dinv, R, beta, S, part, bound);
+}
+
+// Halo lists of the ring SpMM (one per RING_G rows of the solver's matrix),
+// built once per system.
+zi_status ensure_ring(zi_system *sys, hipStream_t s) {
+    if (sys->ring_halo) return ZI_OK;
+    const int steps = (sys->n + RING_G - 1) / RING_G;
+    int32_t *h = nullptr;   // lists, then one path flag per step
+    ZI_TRY(sys->pool.alloc(&h, (size_t)std::max(steps, 1) * (RING_HMAX + 1)));
+    if (steps > 0) {
+        hipLaunchKernelGGL(k_ring_halo, dim3(steps), dim3(256), 0, s, sys->sp_ptr, sys->sp_col,
+                           sys->n, h, h + (size_t)steps * RING_HMAX);
+        ZI_HIP(hipGetLastError());
+    }
+    sys->ring_halo = h;
+    return ZI_OK;
 }
 
 template <int LPR, int NV>
@@ -1651,10 +2055,16 @@ zi_status enqueue_iteration_sr(SolveCtx &c, int k, hipStream_t s) {
     {
         Timed t(c, 0, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
-        ZI_TILE_SWITCH(tile, launch_spmm_sr, g, s, c.sys->sp_ptr, c.sys->sp_col,
-                       (const double *)ws->vs, (const double *)ws->dinv,
-                       (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q, ws->part[0],
-                       (const double *)c.sc.bd);
+        if (kTiles[tile].ring)
+            launch_spmm_sr_ring(g, s, c.sys->ring_halo, c.sys->sp_ptr, c.sys->sp_col,
+                                (const double *)ws->vs, (const double *)ws->dinv,
+                                (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q,
+                                ws->part[0], (const double *)c.sc.bd);
+        else
+            ZI_TILE_SWITCH(tile, launch_spmm_sr, g, s, c.sys->sp_ptr, c.sys->sp_col,
+                           (const double *)ws->vs, (const double *)ws->dinv,
+                           (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q,
+                           ws->part[0], (const double *)c.sc.bd);
     }
     hipLaunchKernelGGL(k_red_alpha_sr, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt,
                        c.ldp);
@@ -1789,6 +2199,13 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
         return ZI_EINVAL;
     }
     c.sr = !c.mixed && o->form != ZI_PCG_CLASSIC;
+    if (kTiles[tile].ring) {
+        if (!c.sr) {
+            set_error("tile %s serves the single-reduction FP64 solver only", kTiles[tile].name);
+            return ZI_EINVAL;
+        }
+        ZI_TRY(ensure_ring(sys, s));
+    }
     ZI_TRY(ensure_ws(sys, ldp, max_nrt(n, ldp)));
     zi_solver_ws *ws = sys->ws;
     c.sys = sys;
@@ -2367,7 +2784,12 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     // after a warm-up: the other kernels of an iteration run with one fixed
     // geometry whatever the tile.
     const bool f32 = precision == ZI_FP32_SPMM_IR;
+    if (!f32) ZI_TRY(ensure_ring(sys, s));
     for (int t = 0; t < NTILES; ++t) {
+        if (f32 && kTiles[t].ring) {   // the ring SpMM has no float32 form
+            if (ms_out) ms_out[t] = -1.0;
+            continue;
+        }
         const Geom gs = make_geom_for(f32 ? GK::SPMM_DOT32 : GK::SPMM_SR, n, ldp, t);
         double total = 0.0;
         const int kinds = 1;
@@ -2386,6 +2808,11 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                     ZI_TILE_SWITCH(t, launch_spmm, gs, s, sys->sp_ptr, sys->sp_col,
                                    (const double *)sys->sp_val, (const float *)P0, Qf,
                                    ws->part[0], (const double *)ws->aring);
+                } else if (kTiles[t].ring) {
+                    launch_spmm_sr_ring(gs, s, sys->ring_halo, sys->sp_ptr, sys->sp_col,
+                                        (const double *)sys->sp_val, (const double *)ws->dinv,
+                                        (const double *)ws->P[0], (const double *)ws->bring,
+                                        ws->Q, ws->part[0], (const double *)ws->aring);
                 } else {   // the FP64 solve's default (single-reduction) kernels
                     ZI_TILE_SWITCH(t, launch_spmm_sr, gs, s, sys->sp_ptr, sys->sp_col,
                                    (const double *)sys->sp_val, (const double *)ws->dinv,
@@ -2424,6 +2851,10 @@ zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double 
     if (tile < 0) tile = auto_tile(k);
     if (tile >= NTILES) {
         set_error("tile %d out of range", tile);
+        return ZI_EINVAL;
+    }
+    if (kTiles[tile].ring) {
+        set_error("tile %s serves the single-reduction solver only", kTiles[tile].name);
         return ZI_EINVAL;
     }
     const int n = sys->n;

@@ -193,6 +193,9 @@ struct zi_system {
 
     int32_t *colmap = nullptr;   // electrode -> solved column for column subsets
 
+    // halo lists of the ring SpMM tile (built on first use)
+    int32_t *ring_halo = nullptr;
+
     // SpMM tile chosen by zi_autotune per precision (for that ldp)
     int32_t tuned_tile[2] = {-1, -1};
     int32_t tuned_ldp[2] = {0, 0};

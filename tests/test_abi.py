@@ -44,7 +44,7 @@ def test_status_strings():
 
 def test_tiles_listed():
     names = zi.tile_names()
-    assert len(names) >= 8 and all(n.startswith("lpr") for n in names)
+    assert len(names) >= 8 and all(n.startswith(("lpr", "ring")) for n in names)
     assert len(set(names)) == len(names)
 
 

