@@ -121,10 +121,7 @@ typedef struct {
                             (the SpMM and updates of every 8th
                             iteration, and every full flush) */
     int32_t tile;        /* SpMM tile id (see zi_tile_count); -1 -> the tile
-                            zi_autotune chose, else a width-based default.
-                            The LDS ring tile serves the single-reduction
-                            FP64 form only; other forms reject it
-                            (ZI_EINVAL) */
+                            zi_autotune chose, else a width-based default */
     int32_t graph;       /* 1: replay the iteration loop as a hipGraph of
                             check_every iterations (no per-kernel timing) */
     const double *x0;    /* n_nodes x L initial iterate, or NULL for zero */
@@ -205,8 +202,7 @@ zi_status zi_transfer_solve_batch(zi_system *const *systems, int32_t n_systems,
  * bit.  Each tile: the best of three launches after a warm-up.  The
  * workspace's contents are overwritten.  best_tile (HOST, may be NULL)
  * receives the choice; ms (HOST, may be NULL, zi_tile_count() entries) the
- * milliseconds per tile, -1 for a tile that the precision cannot use (the
- * LDS ring tile in ZI_FP32_SPMM_IR). */
+ * milliseconds per tile. */
 zi_status zi_autotune(zi_system *sys, int32_t precision, int32_t *best_tile, double *ms,
                       void *hip_stream);
 
@@ -357,7 +353,8 @@ zi_status zi_copy_probe(const double *src, double *dst, int64_t n, double *ms, v
 /* Number of SpMM tile configurations and a description of tile t:
  * lpr<lanes per row>_nv<column pairs per lane>_cw<chunk width>, with _front
  * for the cooperative-front schedule, or ring_g<rows per step>_cw<chunk
- * width> for the LDS ring SpMM of the single-reduction form. */
+ * width> for the LDS ring SpMM of the solver (16 columns of FP64 vectors, 32
+ * of float32 ones, per chunk; not for zi_spmm). */
 int32_t zi_tile_count(void);
 const char *zi_tile_name(int32_t t);
 

@@ -496,7 +496,6 @@ constexpr int RING_H = 64;                          // window reach below and ab
 constexpr int RING_ROWS = RING_G + 2 * RING_H;      // rows held in the LDS ring
 constexpr int RING_HMAX = 32 * RING_HPL;            // halo rows staged per step
 constexpr int RING_HSEARCH = 128;                   // halo list in LDS, padded to a power of 2
-constexpr int RING_CW = 16;                         // columns per chunk (8 lanes x double2)
 constexpr int RING_SORT = 1024;                     // halo candidates sorted per step
 static_assert(RING_HMAX <= RING_HSEARCH, "halo search");
 
@@ -564,28 +563,69 @@ __global__ __launch_bounds__(256) void k_ring_halo(const int32_t *__restrict__ r
     }
 }
 
-// R[row, c..c+1], or 0 where the lane or the row lies outside the block.
-__device__ __forceinline__ double2 ring_row(const double *__restrict__ R, int row, int n, int ldp,
+// A lane of the ring SpMM owns 16 bytes of a row's chunk: RingT<TX>::CPL
+// columns of the block vector type TX, kept in LDS and in registers as the
+// raw 16 bytes (a double2, or four floats in a double2's bits).
+template <class TX>
+struct RingT;
+template <>
+struct RingT<double> {
+    static constexpr int CPL = 2;
+};
+template <>
+struct RingT<float> {
+    static constexpr int CPL = 4;
+};
+
+// The lane's 16 bytes of row `row` (columns c.. of the chunk), 0 where the
+// lane or the row lies outside the block.  Columns come in pairs (ldp is
+// even), so a lane whose last pair lies past ldp loads only its first.
+template <class TX>
+__device__ __forceinline__ double2 ring_row(const TX *__restrict__ X, int row, int n, int ldp,
                                             int c, bool ok) {
     double2 v = make_double2(0.0, 0.0);
-    if (ok && row >= 0 && row < n) v = ld2(R + (size_t)row * ldp + c);
+    if (!(ok && row >= 0 && row < n)) return v;
+    const TX *p = X + (size_t)row * ldp + c;
+    if constexpr (sizeof(TX) == 8) {
+        v = ld2(p);
+    } else {
+        const float2 a = *reinterpret_cast<const float2 *>(p);
+        const float2 b = c + 2 < ldp ? *reinterpret_cast<const float2 *>(p + 2)
+                                     : make_float2(0.f, 0.f);
+        v = make_double2(__builtin_bit_cast(double, a), __builtin_bit_cast(double, b));
+    }
     return v;
 }
 
-// X[col, c..c+1] for the ring SpMM at a step whose window starts at lo: from
+// The lane's columns of a 16-byte unit, widened to double.
+template <class TX>
+__device__ __forceinline__ void ring_cols(double2 v, double (&x)[RingT<TX>::CPL]) {
+    if constexpr (sizeof(TX) == 8) {
+        x[0] = v.x;
+        x[1] = v.y;
+    } else {
+        const float2 a = __builtin_bit_cast(float2, v.x), b = __builtin_bit_cast(float2, v.y);
+        x[0] = a.x;
+        x[1] = a.y;
+        x[2] = b.x;
+        x[3] = b.y;
+    }
+}
+
+// X[col, chunk] for the ring SpMM at a step whose window starts at lo: from
 // the ring when col lies in the window, else from the staged halo rows
 // (lower bound in the sorted, INT_MAX-padded halo list), else from memory.
+template <class TX>
 __device__ __forceinline__ double2 ring_fetch(const double2 (*ring)[8], const double2 (*hrow)[8],
-                                              const int *hidx, const double *__restrict__ R,
-                                              int col, int lo, int pr, int n, int ldp, int c,
-                                              bool ok) {
+                                              const int *hidx, const TX *__restrict__ X, int col,
+                                              int lo, int pr, int n, int ldp, int c, bool ok) {
     if ((unsigned)(col - lo) < (unsigned)RING_ROWS) return ring[col % RING_ROWS][pr];
     int p = 0;
 #pragma unroll
     for (int w = RING_HSEARCH / 2; w > 0; w >>= 1)
         if (hidx[p + w - 1] < col) p += w;
     if (hidx[p] == col) return hrow[p][pr];
-    return ring_row(R, col, n, ldp, c, ok);
+    return ring_row(X, col, n, ldp, c, ok);
 }
 
 // The same where every reference is known to be in the window or the halo.
@@ -601,30 +641,40 @@ __device__ __forceinline__ double2 ring_fetch_staged(const double2 (*ring)[8],
 }
 
 // The next step's loads of one lane: matrix entry (lane pr of the row's
-// group holds entry pr), S and D^-1 of each of its rows.
+// group holds entry pr), D^-1 and the old S of each of its rows.
+template <int CPL>
 struct RingRows {
     int ci[RING_RPL];
     double va[RING_RPL], di[RING_RPL];
-    double2 s[RING_RPL];
+    double s[RING_RPL][CPL];
     int rp[RING_RPL][2];
 };
 
+// Ring SpMM in two forms, on block vectors of type TX (16 columns of double
+// or 32 of float per chunk):
+//   SR (single-reduction PCG, FP64): Y = A D^-1 X + beta Y in place with the
+//      values a_ij / d_j, and the partials of delta = sum (D^-1 X) . W;
+//   !SR (classic PCG): Y = A X with the values a_ij, and the partials of
+//      sum X . Y with X and Y as stored.
 // Block b runs on XCD b mod 8; the ncc chunk blocks of one row range are
 // numbered consecutively on one XCD, so that they run together and share
 // the range's matrix entries (and halo rows) in that XCD's L2.
-__global__ __launch_bounds__(BLOCK) void k_spmm_sr_ring(Geom g, const int32_t *__restrict__ halo,
-                                                        const int32_t *__restrict__ slow,
-                                                        const int32_t *__restrict__ rp,
-                                                        const int32_t *__restrict__ ci,
-                                                        const double *__restrict__ vs,
-                                                        const double *__restrict__ dinv,
-                                                        const double *__restrict__ R,
-                                                        const double *__restrict__ beta,
-                                                        double *__restrict__ S, double *part,
-                                                        const double *__restrict__ bound) {
-    static_assert(Lane<8, 1>::RSTEP == 32 && RING_CW == Lane<8, 1>::CW, "ring lanes");
-    static_assert(RING_HMAX * 8 * sizeof(double2) >= 2 * 32 * RING_CW * sizeof(double),
-                  "the halo rows double as the partial-sum buffer");
+template <class TX, bool SR>
+__global__ __launch_bounds__(BLOCK) void k_spmm_ring(Geom g, const int32_t *__restrict__ halo,
+                                                     const int32_t *__restrict__ slow,
+                                                     const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci,
+                                                     const double *__restrict__ vals,
+                                                     const double *__restrict__ dinv,
+                                                     const TX *__restrict__ X,
+                                                     const double *__restrict__ beta,
+                                                     TX *__restrict__ Y, double *part,
+                                                     const double *__restrict__ bound) {
+    constexpr int CPL = RingT<TX>::CPL;
+    constexpr int CW = 8 * CPL;                 // chunk width
+    static_assert(!SR || sizeof(TX) == 8, "the single-reduction form is FP64");
+    static_assert(2 * 32 * CW * sizeof(double) <= RING_ROWS * 8 * sizeof(double2),
+                  "the ring doubles as the partial-sum buffer");
     if (g.gate && *g.gate == 0) return;
     const int bx = blockIdx.x;
     const int j = bx >> 3;
@@ -634,36 +684,42 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_sr_ring(Geom g, const int32_t *_
     const int a = range * g.rb;                 // a multiple of RING_G
     const int e = min(g.n, a + g.rb);
     const int n = g.n, ldp = g.ldp;
-    const Lane<8, 1> ln(g, cc);
-    const int rl = ln.slot, pr = ln.lr;         // lane group (row rl + 32 k of a step), pair
-    const int c = ln.c[0];
-    const bool ok = ln.ok[0];
+    const int rl = threadIdx.x >> 3, pr = threadIdx.x & 7;   // lane group (rows rl + 32 k), unit
+    const int c = cc * CW + CPL * pr;           // the lane's first column
+    const bool ok = c < ldp;
 
     __shared__ double2 ring[RING_ROWS][8];
     __shared__ double2 hrow[RING_HMAX][8];
     __shared__ int hidx[RING_HSEARCH];
-    __shared__ double m1[RING_CW];              // first fold grid of the chunk's columns
+    __shared__ double m1[CW];                   // first fold grid of the chunk's columns
     const double f2 = ldexp(1.0, g.cl2n - 52);
-    double2 be = make_double2(0.0, 0.0);
-    if (ok && beta) be = ld2(beta + c);
-    const double2 zero = make_double2(0.0, 0.0);
+    double be[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) be[u] = (SR && beta && c + u < ldp) ? beta[c + u] : 0.0;
 
-    // loads of step t's entries, S and D^-1 (row pointers already known)
-    auto load_rows = [&](int t, RingRows &q) {
+    // loads of step t's entries, D^-1 and S (row pointers already known)
+    auto load_rows = [&](int t, RingRows<CPL> &q) {
 #pragma unroll
         for (int k = 0; k < RING_RPL; ++k) {
             q.ci[k] = 0;
             q.va[k] = 0.0;
             q.di[k] = 0.0;
-            q.s[k] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) q.s[k][u] = 0.0;
             const int row = t + rl + 32 * k;
             if (row < e) {
                 if (pr < q.rp[k][1] - q.rp[k][0]) {
                     q.ci[k] = ci[q.rp[k][0] + pr];
-                    q.va[k] = vs[q.rp[k][0] + pr];
+                    q.va[k] = vals[q.rp[k][0] + pr];
                 }
-                q.di[k] = dinv[row];
-                if (ok && beta) q.s[k] = ldn2(S + (size_t)row * ldp + c);
+                if constexpr (SR) {
+                    q.di[k] = dinv[row];
+                    if (ok && beta) {
+                        const double2 v = ldn2(Y + (size_t)row * ldp + c);
+                        q.s[k][0] = v.x;
+                        q.s[k][1] = v.y;
+                    }
+                }
             }
         }
     };
@@ -677,17 +733,15 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_sr_ring(Geom g, const int32_t *_
     };
 
     // window and halo of the first step
-    if (threadIdx.x < RING_CW) {
-        const int col = cc * RING_CW + threadIdx.x;
+    if (threadIdx.x < CW) {
+        const int col = cc * CW + threadIdx.x;
         m1[threadIdx.x] = col < ldp ? fold_grid(bound[col]) : 0.0;
     }
     for (int i = threadIdx.x; i < RING_ROWS * 8; i += BLOCK) {
         const int row = a - RING_H + (i >> 3);
         if (row >= 0) {
-            const int col = cc * RING_CW + 2 * (i & 7);
-            double2 v = zero;
-            if (row < n && col < ldp) v = ld2(R + (size_t)row * ldp + col);
-            ring[row % RING_ROWS][i & 7] = v;
+            const int cu = cc * CW + CPL * (i & 7);
+            ring[row % RING_ROWS][i & 7] = ring_row(X, row, n, ldp, cu, cu < ldp);
         }
     }
     for (int i = threadIdx.x; i < RING_HSEARCH; i += BLOCK)
@@ -696,9 +750,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_sr_ring(Geom g, const int32_t *_
 #pragma unroll
     for (int k = 0; k < RING_HPL; ++k) {
         const int h = hidx[rl + 32 * k];
-        hrow[rl + 32 * k][pr] = ring_row(R, h != INT_MAX ? h : -1, n, ldp, c, ok);
+        hrow[rl + 32 * k][pr] = ring_row(X, h != INT_MAX ? h : -1, n, ldp, c, ok);
     }
-    RingRows cur, nxt;
+    RingRows<CPL> cur, nxt;
     load_rp(a, cur.rp);
     load_rp(a + RING_G, nxt.rp);
     load_rows(a, cur);
@@ -711,31 +765,33 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_sr_ring(Geom g, const int32_t *_
     int slow_n = a + RING_G < e ? slow[a / RING_G + 1] : 0;
     __syncthreads();
 
-    double2 dot0 = zero, dot1 = zero;           // the two fold sums of delta
+    double dot0[CPL], dot1[CPL];                 // the two fold sums of the dot product
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) dot0[u] = dot1[u] = 0.0;
     for (int s = a; s < e; s += RING_G) {
         const int t = s + RING_G;               // the next step
         const bool has_t = t < e;
         // next step: new ring rows, halo rows, entries, S, D^-1; the step
-        // after: row pointers and halo indices
+        // after: row pointers, halo indices and path
         double2 rn[RING_RPL], hn[RING_HPL];
         int hi_nn[RING_HPL], rp_nn[RING_RPL][2], slow_nn = 0;
 #pragma unroll
         for (int k = 0; k < RING_RPL; ++k) {
-            rn[k] = zero;
+            rn[k] = make_double2(0.0, 0.0);
             rp_nn[k][0] = rp_nn[k][1] = 0;
         }
 #pragma unroll
         for (int k = 0; k < RING_HPL; ++k) {
-            hn[k] = zero;
+            hn[k] = make_double2(0.0, 0.0);
             hi_nn[k] = INT_MAX;
         }
         if (has_t) {
 #pragma unroll
             for (int k = 0; k < RING_RPL; ++k)
-                rn[k] = ring_row(R, t + RING_H + rl + 32 * k, n, ldp, c, ok);
+                rn[k] = ring_row(X, t + RING_H + rl + 32 * k, n, ldp, c, ok);
 #pragma unroll
             for (int k = 0; k < RING_HPL; ++k)
-                hn[k] = ring_row(R, hi_n[k] != INT_MAX ? hi_n[k] : -1, n, ldp, c, ok);
+                hn[k] = ring_row(X, hi_n[k] != INT_MAX ? hi_n[k] : -1, n, ldp, c, ok);
             load_rows(t, nxt);
             const int u = t + RING_G;
             if (u < e) {
@@ -756,35 +812,53 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_sr_ring(Geom g, const int32_t *_
         for (int k = 0; k < RING_RPL; ++k) {
             const int row = s + rl + 32 * k;
             if (row >= e) continue;
-            double2 acc = zero;
+            double acc[CPL];
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) acc[u] = 0.0;
             if (!slow_c) {
                 const int cnt = cur.rp[k][1] - cur.rp[k][0];
                 for (int q = 0; q < cnt; ++q) {
                     const int col = __shfl(cur.ci[k], q, 8);
                     const double av = __shfl(cur.va[k], q, 8);
-                    const double2 xv = ring_fetch_staged(ring, hrow, hidx, col, lo, pr);
-                    acc.x = fma(av, xv.x, acc.x);
-                    acc.y = fma(av, xv.y, acc.y);
+                    double xv[CPL];
+                    ring_cols<TX>(ring_fetch_staged(ring, hrow, hidx, col, lo, pr), xv);
+#pragma unroll
+                    for (int u = 0; u < CPL; ++u) acc[u] = fma(av, xv[u], acc[u]);
                 }
             } else {
                 for (int q = cur.rp[k][0]; q < cur.rp[k][1]; ++q) {
                     const int col = ci[q];
-                    const double av = vs[q];
-                    const double2 xv = ring_fetch(ring, hrow, hidx, R, col, lo, pr, n, ldp, c, ok);
-                    acc.x = fma(av, xv.x, acc.x);
-                    acc.y = fma(av, xv.y, acc.y);
+                    const double av = vals[q];
+                    double xv[CPL];
+                    ring_cols<TX>(ring_fetch(ring, hrow, hidx, X, col, lo, pr, n, ldp, c, ok), xv);
+#pragma unroll
+                    for (int u = 0; u < CPL; ++u) acc[u] = fma(av, xv[u], acc[u]);
                 }
             }
             if (ok) {
-                double2 sn;
-                sn.x = fma(be.x, cur.s[k].x, acc.x);
-                sn.y = fma(be.y, cur.s[k].y, acc.y);
-                stn2(S + (size_t)row * ldp + c, sn);
-                // the row itself lies in the window
-                const double2 xs = ring[row % RING_ROWS][pr];
-                const int cl = 2 * pr;
-                fold_add(xs.x * cur.di[k], acc.x, m1[cl], f2, dot0.x, dot1.x);
-                fold_add(xs.y * cur.di[k], acc.y, m1[cl + 1], f2, dot0.y, dot1.y);
+                double xs[CPL];                 // the row itself lies in the window
+                ring_cols<TX>(ring[row % RING_ROWS][pr], xs);
+                TX *y = Y + (size_t)row * ldp + c;
+                if constexpr (SR) {
+                    double2 sn;
+                    sn.x = fma(be[0], cur.s[k][0], acc[0]);
+                    sn.y = fma(be[1], cur.s[k][1], acc[1]);
+                    stn2(y, sn);
+                    const int cl = CPL * pr;
+                    fold_add(xs[0] * cur.di[k], acc[0], m1[cl], f2, dot0[0], dot1[0]);
+                    fold_add(xs[1] * cur.di[k], acc[1], m1[cl + 1], f2, dot0[1], dot1[1]);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < CPL; u += 2) {
+                        if (c + u >= ldp) break;
+                        const double2 q2 = make_double2(acc[u], acc[u + 1]);
+                        stpair_nt(y + u, q2);
+                        const double2 qs = as_stored(q2, (const TX *)y);
+                        const int cl = CPL * pr + u;
+                        fold_add(xs[u], qs.x, m1[cl], f2, dot0[u], dot1[u]);
+                        fold_add(xs[u + 1], qs.y, m1[cl + 1], f2, dot0[u + 1], dot1[u + 1]);
+                    }
+                }
             }
         }
         __syncthreads();
@@ -812,16 +886,17 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_sr_ring(Geom g, const int32_t *_
     }
 
     // partials of the range, summed over the block's lane groups in a fixed
-    // order (the halo rows serve as the buffer: the loop ended on a barrier)
-    double(*red)[32][RING_CW] = reinterpret_cast<double(*)[32][RING_CW]>(&hrow[0][0]);
-    red[0][rl][2 * pr] = dot0.x;
-    red[0][rl][2 * pr + 1] = dot0.y;
-    red[1][rl][2 * pr] = dot1.x;
-    red[1][rl][2 * pr + 1] = dot1.y;
+    // order (the ring serves as the buffer: the loop ended on a barrier)
+    double(*red)[32][CW] = reinterpret_cast<double(*)[32][CW]>(&ring[0][0]);
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        red[0][rl][CPL * pr + u] = dot0[u];
+        red[1][rl][CPL * pr + u] = dot1[u];
+    }
     __syncthreads();
-    if (threadIdx.x < 2 * RING_CW) {
-        const int q = threadIdx.x / RING_CW, cl = threadIdx.x % RING_CW;
-        const int col = cc * RING_CW + cl;
+    if (threadIdx.x < 2 * CW) {
+        const int q = threadIdx.x / CW, cl = threadIdx.x % CW;
+        const int col = cc * CW + cl;
         if (col < ldp) {
             double sum = 0.0;
             for (int k = 0; k < 32; ++k) sum += red[q][k][cl];
@@ -1445,9 +1520,10 @@ int auto_tile(int ldp) {
 // ones have finished would sweep the range a second time, behind the first
 // front, and fetch every shared neighbour row again.
 constexpr int SLAB_STEPS = 64;
-Geom make_geom(int n, int ldp, int tile, int resident = 0, int slabs = 1) {
+// ring_cw: the ring tile's chunk width (16 columns of double, 32 of float).
+Geom make_geom(int n, int ldp, int tile, int resident = 0, int slabs = 1, int ring_cw = 16) {
     const TileCfg &t = kTiles[tile];
-    const int cw = 2 * t.lpr * t.nv;
+    const int cw = t.ring ? ring_cw : 2 * t.lpr * t.nv;
     const int rstep = WAVES * (64 / t.lpr);
     Geom g{};
     g.n = n;
@@ -1534,7 +1610,9 @@ int resident_blocks(GK k, int tile) {
     int &r = cache[(int)k][tile];
     if (r == 0) {
         if (kTiles[tile].ring)
-            r = resident_per_xcd(k_spmm_sr_ring);
+            r = k == GK::SPMM_DOT32   ? resident_per_xcd(k_spmm_ring<float, false>)
+                : k == GK::SPMM_DOT64 ? resident_per_xcd(k_spmm_ring<double, false>)
+                                      : resident_per_xcd(k_spmm_ring<double, true>);
         else
             ZI_TILE_SWITCH(tile, occupancy_of, k, &r);
     }
@@ -1555,7 +1633,8 @@ int spmm_slabs(GK k) {
 }
 
 Geom make_geom_for(GK k, int n, int ldp, int tile) {
-    return make_geom(n, ldp, tile, resident_blocks(k, tile), std::min(MAX_SLABS, spmm_slabs(k)));
+    return make_geom(n, ldp, tile, resident_blocks(k, tile), std::min(MAX_SLABS, spmm_slabs(k)),
+                     k == GK::SPMM_DOT32 ? 32 : 16);
 }
 
 template <int LPR, int NV, class TV, class TX>
@@ -1590,13 +1669,15 @@ void launch_spmm_sr(const Geom &g, hipStream_t s, const int32_t *rp, const int32
                            vs, dinv, R, beta, S, part, bound);
 }
 
-// halo: the system's ring lists (ring_halo), followed by the steps' path flags.
-void launch_spmm_sr_ring(const Geom &g, hipStream_t s, const int32_t *halo, const int32_t *rp,
-                         const int32_t *ci, const double *vs, const double *dinv, const double *R,
-                         const double *beta, double *S, double *part, const double *bound) {
+// halo: the system's ring lists (ring_halo), followed by the steps' path
+// flags.  SR: Y = A D^-1 X + beta Y (vals = a_ij / d_j); else Y = A X.
+template <class TX, bool SR>
+void launch_spmm_ring(const Geom &g, hipStream_t s, const int32_t *halo, const int32_t *rp,
+                      const int32_t *ci, const double *vals, const double *dinv, const TX *X,
+                      const double *beta, TX *Y, double *part, const double *bound) {
     const size_t steps = ((size_t)g.n + RING_G - 1) / RING_G;
-    hipLaunchKernelGGL(k_spmm_sr_ring, dim3(g.nb_pad), dim3(BLOCK), 0, s, g, halo,
-                       halo + steps * RING_HMAX, rp, ci, vs, dinv, R, beta, S, part, bound);
+    hipLaunchKernelGGL((k_spmm_ring<TX, SR>), dim3(g.nb_pad), dim3(BLOCK), 0, s, g, halo,
+                       halo + steps * RING_HMAX, rp, ci, vals, dinv, X, beta, Y, part, bound);
 }
 
 // Halo lists of the ring SpMM (one per RING_G rows of the solver's matrix),
@@ -1809,6 +1890,7 @@ int max_nrt(int n, int ldp) {
     for (int t = 0; t < NTILES; ++t) {
         const Geom g = make_geom(n, ldp, t);
         m = std::max(m, g.front ? MAX_SLABS * g.nrt : g.nrt);
+        if (kTiles[t].ring) m = std::max(m, make_geom(n, ldp, t, 0, 1, 32).nrt);
     }
     return m;
 }
@@ -1846,6 +1928,8 @@ struct SolveCtx {
     int32_t *gate_out = nullptr;  // batched heads: (gate, breakdown) for the host
     int tile = 0, ldp = 0, L = 0, maxit = 0, check = 0;
     int stile = 0;            // the streaming kernels' tile (a function of ldp)
+    int rtile = 0;            // tile and geometry of the product A X of the true residual
+    Geom grt{};               // (the SpMM tile's, or the streaming tile's for the ring tile)
     double tol = 0, tol2 = 0;
     double eta2 = 0;          // inner-cycle reduction (squared); 0 = run to tol
     bool mixed = false, timing = false;
@@ -1983,8 +2067,13 @@ zi_status enqueue_iteration(SolveCtx &c, int k, const double *va, hipStream_t s,
     {
         Timed t(c, 0, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
-        ZI_TILE_SWITCH(tile, launch_spmm, g, s, c.sys->sp_ptr, c.sys->sp_col, va, (const TP *)Pk,
-                       Q, ws->part[0], (const double *)c.sc.bd);
+        if (kTiles[tile].ring)
+            launch_spmm_ring<TP, false>(g, s, c.sys->ring_halo, c.sys->sp_ptr, c.sys->sp_col, va,
+                                        nullptr, (const TP *)Pk, nullptr, Q, ws->part[0],
+                                        (const double *)c.sc.bd);
+        else
+            ZI_TILE_SWITCH(tile, launch_spmm, g, s, c.sys->sp_ptr, c.sys->sp_col, va,
+                           (const TP *)Pk, Q, ws->part[0], (const double *)c.sc.bd);
     }
     hipLaunchKernelGGL(k_red_alpha, dim3(c.ldp), dim3(RED), 0, s, c.sc, al, ws->part[0], g.nrt,
                        c.ldp);
@@ -2056,10 +2145,11 @@ zi_status enqueue_iteration_sr(SolveCtx &c, int k, hipStream_t s) {
         Timed t(c, 0, s, k % TIMING_STRIDE == 0);
         ZI_TRY(t.st);
         if (kTiles[tile].ring)
-            launch_spmm_sr_ring(g, s, c.sys->ring_halo, c.sys->sp_ptr, c.sys->sp_col,
-                                (const double *)ws->vs, (const double *)ws->dinv,
-                                (const double *)c.Rsr(k), (const double *)c.sc.beta, ws->Q,
-                                ws->part[0], (const double *)c.sc.bd);
+            launch_spmm_ring<double, true>(g, s, c.sys->ring_halo, c.sys->sp_ptr,
+                                           c.sys->sp_col, (const double *)ws->vs,
+                                           (const double *)ws->dinv, (const double *)c.Rsr(k),
+                                           (const double *)c.sc.beta, ws->Q, ws->part[0],
+                                           (const double *)c.sc.bd);
         else
             ZI_TILE_SWITCH(tile, launch_spmm_sr, g, s, c.sys->sp_ptr, c.sys->sp_col,
                            (const double *)ws->vs, (const double *)ws->dinv,
@@ -2109,7 +2199,7 @@ zi_status flush_all(SolveCtx &c, hipStream_t s) {
 // Q is used as FP64 scratch (its float32 half is rewritten by the next SpMM).
 zi_status true_residual(SolveCtx &c, hipStream_t s, bool write_r) {
     zi_solver_ws *ws = c.ws;
-    ZI_TILE_SWITCH(c.tile, launch_spmm, c.g, s, c.sys->sp_ptr, c.sys->sp_col,
+    ZI_TILE_SWITCH(c.rtile, launch_spmm, c.grt, s, c.sys->sp_ptr, c.sys->sp_col,
                    (const double *)c.sys->sp_val, (const double *)ws->X, ws->Q, (double *)nullptr);
     if (c.mixed) {   // R holds float32 in the mixed mode
         ZI_TILE_SWITCH(c.stile, launch_residual, c.gr, s, c.sys, (const int32_t *)c.colmap,
@@ -2199,13 +2289,7 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
         return ZI_EINVAL;
     }
     c.sr = !c.mixed && o->form != ZI_PCG_CLASSIC;
-    if (kTiles[tile].ring) {
-        if (!c.sr) {
-            set_error("tile %s serves the single-reduction FP64 solver only", kTiles[tile].name);
-            return ZI_EINVAL;
-        }
-        ZI_TRY(ensure_ring(sys, s));
-    }
+    if (kTiles[tile].ring) ZI_TRY(ensure_ring(sys, s));
     ZI_TRY(ensure_ws(sys, ldp, max_nrt(n, ldp)));
     zi_solver_ws *ws = sys->ws;
     c.sys = sys;
@@ -2213,12 +2297,14 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     c.g = make_geom_for(c.sr ? GK::SPMM_SR : c.mixed ? GK::SPMM_DOT32 : GK::SPMM_DOT64, n, ldp,
                         tile);
     c.stile = stream_tile(ldp);
+    c.rtile = kTiles[tile].ring ? c.stile : tile;
+    c.grt = kTiles[tile].ring ? make_geom_for(GK::SPMM64, n, ldp, c.rtile) : c.g;
     c.gu = make_geom_for(c.mixed ? GK::UPDATE32 : GK::UPDATE64, n, ldp, c.stile);
     c.gp = make_geom_for(c.mixed ? GK::PUPDATE32 : GK::PUPDATE64, n, ldp, c.stile);
     c.gr = make_geom_for(c.mixed ? GK::RESIDUAL32 : GK::RESIDUAL64, n, ldp, c.stile);
     if (gated) {
         c.gate = ws->gate;
-        c.g.gate = c.gu.gate = c.gp.gate = c.gr.gate = c.gate;
+        c.g.gate = c.gu.gate = c.gp.gate = c.gr.gate = c.grt.gate = c.gate;
         ZI_TRY(open_gate(c, s));
     }
     c.tile = tile;
@@ -2784,12 +2870,8 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
     // after a warm-up: the other kernels of an iteration run with one fixed
     // geometry whatever the tile.
     const bool f32 = precision == ZI_FP32_SPMM_IR;
-    if (!f32) ZI_TRY(ensure_ring(sys, s));
+    ZI_TRY(ensure_ring(sys, s));
     for (int t = 0; t < NTILES; ++t) {
-        if (f32 && kTiles[t].ring) {   // the ring SpMM has no float32 form
-            if (ms_out) ms_out[t] = -1.0;
-            continue;
-        }
         const Geom gs = make_geom_for(f32 ? GK::SPMM_DOT32 : GK::SPMM_SR, n, ldp, t);
         double total = 0.0;
         const int kinds = 1;
@@ -2805,14 +2887,22 @@ zi_status zi_autotune_impl(zi_system *sys, int32_t precision, int32_t *best, dou
                     (void)kind;
                     (void)P1;
                     (void)Rf;
-                    ZI_TILE_SWITCH(t, launch_spmm, gs, s, sys->sp_ptr, sys->sp_col,
-                                   (const double *)sys->sp_val, (const float *)P0, Qf,
-                                   ws->part[0], (const double *)ws->aring);
+                    if (kTiles[t].ring)
+                        launch_spmm_ring<float, false>(gs, s, sys->ring_halo, sys->sp_ptr,
+                                                       sys->sp_col, (const double *)sys->sp_val,
+                                                       nullptr, (const float *)P0, nullptr, Qf,
+                                                       ws->part[0], (const double *)ws->aring);
+                    else
+                        ZI_TILE_SWITCH(t, launch_spmm, gs, s, sys->sp_ptr, sys->sp_col,
+                                       (const double *)sys->sp_val, (const float *)P0, Qf,
+                                       ws->part[0], (const double *)ws->aring);
                 } else if (kTiles[t].ring) {
-                    launch_spmm_sr_ring(gs, s, sys->ring_halo, sys->sp_ptr, sys->sp_col,
-                                        (const double *)sys->sp_val, (const double *)ws->dinv,
-                                        (const double *)ws->P[0], (const double *)ws->bring,
-                                        ws->Q, ws->part[0], (const double *)ws->aring);
+                    launch_spmm_ring<double, true>(gs, s, sys->ring_halo, sys->sp_ptr,
+                                                   sys->sp_col, (const double *)sys->sp_val,
+                                                   (const double *)ws->dinv,
+                                                   (const double *)ws->P[0],
+                                                   (const double *)ws->bring, ws->Q, ws->part[0],
+                                                   (const double *)ws->aring);
                 } else {   // the FP64 solve's default (single-reduction) kernels
                     ZI_TILE_SWITCH(t, launch_spmm_sr, gs, s, sys->sp_ptr, sys->sp_col,
                                    (const double *)sys->sp_val, (const double *)ws->dinv,
@@ -2854,7 +2944,7 @@ zi_status zi_spmm_impl(const zi_system *sys, int32_t k, const double *X, double 
         return ZI_EINVAL;
     }
     if (kTiles[tile].ring) {
-        set_error("tile %s serves the single-reduction solver only", kTiles[tile].name);
+        set_error("tile %s serves the solver's products only", kTiles[tile].name);
         return ZI_EINVAL;
     }
     const int n = sys->n;

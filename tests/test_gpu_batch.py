@@ -109,8 +109,6 @@ def test_every_tile_gives_the_same_bits(form, precision):
     for t, name in enumerate(zi.tile_names()):
         if t == 0:
             continue
-        if name.startswith("ring") and (form == "classic" or precision != "fp64"):
-            continue   # the ring SpMM serves the single-reduction FP64 form only
         T, st = g.transfer_solve(tol=1e-8, tile=t, form=form, precision=precision)
         assert np.array_equal(st["iters"], s0["iters"]), (t, zi.tile_names()[t])
         assert torch.equal(T, T0), (t, zi.tile_names()[t], (T - T0).abs().max().item())

@@ -100,7 +100,7 @@ def test_spmm_every_tile(case):
     outs = []
     for t, name in enumerate(zi.tile_names()):
         if name.startswith("ring"):
-            continue   # the ring SpMM serves the single-reduction solver only
+            continue   # the ring SpMM serves the solver's products only
         Y, _ = g.spmm(Xd, tile=t)
         Y = Y.cpu().numpy()
         assert np.abs(Y - ref).max() <= 1e-14 * np.abs(ref).max()

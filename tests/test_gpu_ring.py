@@ -1,11 +1,13 @@
-"""The LDS ring SpMM tile of the single-reduction solver (App. A.4,
-Sec. 2.3.1): T and the iteration counts must be bitwise those of a front
-tile, since every tile forms the products in CSR order and sums the dot
-products on fixed grids.  Cases: the 2 mm sphere (the window covers almost
-every reference), tensor conductivity (many rows of more than eight entries,
-the ring kernel's long-row path), a mesh stretched along z (pencil layers
-longer than the window: most references come from the halo lists or, where
-a list is full, from memory), batched heads, and the forms the tile does not
+"""The LDS ring SpMM tile of the solver (App. A.4, Sec. 2.3.1): T and the
+iteration counts must be bitwise those of a front tile, in the
+single-reduction and classic FP64 forms and in mixed precision (float32
+vectors, 32 columns per chunk), since every tile forms the products in CSR
+order and sums the dot products on fixed grids.  Cases: the 2 mm sphere (the
+window covers almost every reference), tensor conductivity (many rows of
+more than eight entries, the ring kernel's path that reads memory in the row
+loop), a mesh stretched along z (pencil layers longer than the window: most
+references come from the halo lists or, where a list is full, from memory),
+a ragged column count, batched heads, and zi_spmm, which the tile does not
 serve."""
 import numpy as np
 import pytest
@@ -31,8 +33,9 @@ def _tiles():
 
 def _same_as_front(g, what, **kw):
     ring, front = _tiles()
-    T0, s0 = g.transfer_solve(tol=1e-8, tile=front, form="single", **kw)
-    T1, s1 = g.transfer_solve(tol=1e-8, tile=ring, form="single", **kw)
+    kw.setdefault("form", "single")
+    T0, s0 = g.transfer_solve(tol=1e-8, tile=front, **kw)
+    T1, s1 = g.transfer_solve(tol=1e-8, tile=ring, **kw)
     say(f"[ring] {what}: iterations {s1['iters'].min()}..{s1['iters'].max()}, "
         f"true residual max {s1['relres_true'].max():.2e}")
     assert s1["tile"] == ring and s0["tile"] == front
@@ -47,7 +50,18 @@ def test_ring_2mm_matches_front():
     H = hm.workload("sphere2mm_L128")
     say(f"[case] ring tile, 2 mm sphere: n={H.n} L={H.L}")
     g = zi.System.from_head(H)
-    _same_as_front(g, "2 mm")
+    _same_as_front(g, "2 mm, single-reduction")
+    _same_as_front(g, "2 mm, mixed precision", form="auto", precision="fp32_spmm_ir")
+    g.close()
+
+
+@pytest.mark.parametrize("form,precision", [("classic", "fp64"), ("auto", "fp32_spmm_ir")])
+def test_ring_classic_and_mixed_ragged(form, precision):
+    from paper_1811_07717_amd import zi
+    H = hm.workload("sphere8mm_L37")
+    say(f"[case] ring tile, {form} {precision}, L={H.L}")
+    g = zi.System.from_head(H)
+    _same_as_front(g, f"{form} {precision}", form=form, precision=precision)
     g.close()
 
 
@@ -81,6 +95,7 @@ def test_ring_stretched_mesh():
     c = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     g = zi.System(c(nodes), c(H.tets), c(H.sigma), c(H.tris), c(H.tri_electrode), H.Z)
     _same_as_front(g, "stretched")
+    _same_as_front(g, "stretched, mixed precision", form="auto", precision="fp32_spmm_ir")
     g.close()
 
 
@@ -99,18 +114,16 @@ def test_ring_batched_heads():
         g.close()
 
 
-def test_ring_rejected_where_it_does_not_apply():
+def test_ring_not_for_zi_spmm():
     from paper_1811_07717_amd import zi
     ring, _ = _tiles()
     H = hm.workload("sphere8mm_L32")
     g = zi.System.from_head(H)
-    for kw in ({"form": "classic"}, {"precision": "fp32_spmm_ir"}):
-        with pytest.raises(zi.ZiError, match="single-reduction"):
-            g.transfer_solve(tol=1e-8, tile=ring, **kw)
     X = torch.zeros((H.n, 32), dtype=torch.float64, device="cuda")
-    with pytest.raises(zi.ZiError, match="single-reduction"):
+    with pytest.raises(zi.ZiError, match="solver's products only"):
         g.spmm(X, tile=ring)
-    # the mixed-precision autotuner does not score it
-    best, ms = g.autotune(precision="fp32_spmm_ir")
-    assert ms[ring] == -1.0 and best != ring
+    # both precisions score it
+    for prec in ("fp64", "fp32_spmm_ir"):
+        best, ms = g.autotune(precision=prec)
+        assert ms[ring] > 0
     g.close()
