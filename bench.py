@@ -407,7 +407,8 @@ def main():
                                "timed_launches": v["launches"]} for k, v in ktot.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                     "traffic": traffic_for(dom, a.workload, zi.tile_names()[stats[-1]["tile"]])},
+                     "traffic": traffic_for(dom, a.workload + ("" if a.precision == "fp64" else "_mixed"),
+                                            zi.tile_names()[stats[-1]["tile"]])},
     }
     rf = out["roofline"]
     if rf["traffic"]:
