@@ -18,9 +18,11 @@ import numpy as np
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 
-def measure(count=64, precision="fp64", log=None):
+def measure(count=64, precision="fp64", log=None, markers=False):
     """Solve the transfer matrices of `count` uneven heads one after the other
-    and then in one zi_transfer_solve_batch call; returns the figures."""
+    and then in one zi_transfer_solve_batch call; returns the figures.
+    markers: launch the library's copy kernel on a small block before, between
+    and after the two phases, so that a kernel trace can be cut into them."""
     import torch
 
     from paper_1811_07717_amd import headmodel as hm, zi
@@ -31,6 +33,15 @@ def measure(count=64, precision="fp64", log=None):
     tiles = [g.autotune(precision)[0] for g in systems]
     torch.cuda.synchronize()
     solves = sum(H.L for H in heads)
+    mark_src = torch.zeros(1 << 16, dtype=torch.float64, device="cuda")
+    mark_dst = torch.empty_like(mark_src)
+
+    def mark():
+        if markers:
+            zi.copy_probe(mark_src, mark_dst)
+            torch.cuda.synchronize()
+
+    mark()
     say("sequential")
     t0 = time.perf_counter()
     seq_iters = []
@@ -41,11 +52,13 @@ def measure(count=64, precision="fp64", log=None):
         seq_T.append(T)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
+    mark()
     say("one batch")
     t0 = time.perf_counter()
     Ts, stats, rc = zi.transfer_solve_batch(systems, tol=1e-8, precision=precision)
     torch.cuda.synchronize()
     t_bat = time.perf_counter() - t0
+    mark()
     res = max(float(s["relres_true"].max()) for s in stats)
     same = all(torch.equal(a, b) for a, b in zip(Ts, seq_T))
     out = {"heads": count, "precision": precision, "electrode_solves": solves,
@@ -65,8 +78,10 @@ def main():
     p = argparse.ArgumentParser()
     p.add_argument("--heads", type=int, default=64)
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32_spmm_ir"])
+    p.add_argument("--markers", action="store_true",
+                   help="mark the phases with copy kernels (for a kernel trace)")
     a = p.parse_args()
-    out = measure(a.heads, a.precision)
+    out = measure(a.heads, a.precision, markers=a.markers)
     out["metric"] = "electrode-solves/s at rel.resid 1e-8, uneven heads"
     print(json.dumps(out))
 

@@ -22,6 +22,7 @@ import hashlib
 import json
 import os
 import re
+import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_1811_07717_amd/csrc/k_pcg.hip",
@@ -87,8 +88,56 @@ def summarize(fetch_csv, write_csv, copy_mib, spmm_args=None):
     return out, ff, wf
 
 
+def phase_gaps(trace_csv, marker="k_copy2"):
+    """Busy and idle time of the GPU in a rocprofv3 kernel trace, cut into
+    phases at the dispatches of `marker`: per phase the span from the first
+    kernel's start to the last kernel's end, the time some kernel runs (the
+    union of the kernels' intervals on all queues), the rest (idle), the
+    dispatch count and the longest idle stretches (microseconds)."""
+    rows = []
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    phases, cur = [], []
+    for s, e, name in rows:
+        if marker in name:
+            phases.append(cur)
+            cur = []
+        else:
+            cur.append((s, e))
+    phases.append(cur)
+    out = []
+    for ph in phases:
+        if not ph:
+            out.append(None)
+            continue
+        busy, gaps, lo, hi = 0, [], ph[0][0], ph[0][1]
+        for s, e in ph[1:]:
+            if s > hi:
+                busy += hi - lo
+                gaps.append(s - hi)
+                lo, hi = s, e
+            else:
+                hi = max(hi, e)
+        busy += hi - lo
+        span = max(e for _, e in ph) - ph[0][0]
+        gaps.sort(reverse=True)
+        out.append(dict(span_us=span / 1e3, busy_us=busy / 1e3, idle_us=(span - busy) / 1e3,
+                        dispatches=len(ph), gaps_over_50us=sum(g > 50e3 for g in gaps),
+                        longest_gaps_us=[round(g / 1e3, 1) for g in gaps[:5]]))
+    return out
+
+
 def main():
     p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    if "--gaps" in sys.argv:   # phase busy/idle table of a kernel trace
+        g = argparse.ArgumentParser()
+        g.add_argument("--gaps", required=True, help="rocprofv3 run_kernel_trace.csv")
+        g.add_argument("--marker", default="k_copy2")
+        ga = g.parse_args()
+        print(json.dumps(phase_gaps(ga.gaps, ga.marker), indent=1))
+        return
     p.add_argument("--fetch", required=True)
     p.add_argument("--write", required=True)
     p.add_argument("--copy-mib", type=float, required=True,

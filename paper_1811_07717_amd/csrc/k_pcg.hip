@@ -2432,7 +2432,26 @@ zi_status solve_check(SolveCtx &c, hipStream_t s) {
     return solve_check_taken(c, s);
 }
 
-zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
+// Host copies of a solve's final counts and norms (ldp entries each, and the
+// breakdown flag), written by solve_end_enqueue, read by solve_end_finish
+// once the stream has drained.
+struct EndCopy {
+    int32_t *iters = nullptr, *flag = nullptr;
+    double *rr = nullptr, *bb = nullptr, *tr = nullptr;
+    static size_t bytes(int ldp) { return (size_t)ldp * (sizeof(int32_t) + 3 * sizeof(double)) + 8; }
+    void carve(void *p, int ldp) {   // from bytes(ldp) host bytes at p (8-byte aligned)
+        char *q = static_cast<char *>(p);
+        rr = reinterpret_cast<double *>(q);
+        bb = rr + ldp;
+        tr = bb + ldp;
+        iters = reinterpret_cast<int32_t *>(tr + ldp);
+        flag = iters + ldp;
+    }
+};
+
+// The final flush, T in the caller's order and the statistics' copies, queued.
+zi_status solve_end_enqueue(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s,
+                            const EndCopy &h) {
     zi_solver_ws *ws = c.ws;
     const int n = c.sys->n, L = c.L, ldp = c.ldp;
     const bool timing = c.timing;
@@ -2441,22 +2460,37 @@ zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
     ZI_TRY(flush_all(c, s));
     c.timing = timing;
     ZI_TRY(gather_rows(ws->X, ldp, c.sys->iperm, T, L, n, L, s));
-    std::vector<int32_t> h_iters(ldp);
-    std::vector<double> h_rr(ldp), h_bb(ldp), h_true(ldp);
-    ZI_HIP(hipMemcpyAsync(h_iters.data(), c.sc.iters, sizeof(int32_t) * ldp, hipMemcpyDeviceToHost, s));
-    ZI_HIP(hipMemcpyAsync(h_rr.data(), c.sc.rr, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
-    ZI_HIP(hipMemcpyAsync(h_bb.data(), c.sc.bb, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(h.iters, c.sc.iters, sizeof(int32_t) * ldp, hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(h.rr, c.sc.rr, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(h.bb, c.sc.bb, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
     if (st && st->relres_true) {
         ZI_TRY(true_residual(c, s, false));
         hipLaunchKernelGGL(k_red_sum, dim3(ldp), dim3(RED), 0, s, ws->part[2], c.gr.nrt,
                            c.sc.alpha);   // alpha reused as scratch
         ZI_HIP(hipGetLastError());
-        ZI_HIP(hipMemcpyAsync(h_true.data(), c.sc.alpha, sizeof(double) * ldp,
-                              hipMemcpyDeviceToHost, s));
+        ZI_HIP(hipMemcpyAsync(h.tr, c.sc.alpha, sizeof(double) * ldp, hipMemcpyDeviceToHost, s));
     }
-    int32_t h_flag = 0;
-    ZI_HIP(hipMemcpyAsync(&h_flag, c.sc.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ZI_HIP(hipMemcpyAsync(h.flag, c.sc.flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    return ZI_OK;
+}
+
+zi_status solve_end_finish(SolveCtx &c, zi_solve_stats *st, const EndCopy &h);
+
+zi_status solve_end(SolveCtx &c, double *T, zi_solve_stats *st, hipStream_t s) {
+    std::vector<double> buf((EndCopy::bytes(c.ldp) + 7) / 8);
+    EndCopy h;
+    h.carve(buf.data(), c.ldp);
+    ZI_TRY(solve_end_enqueue(c, T, st, s, h));
     ZI_HIP(hipStreamSynchronize(s));
+    return solve_end_finish(c, st, h);
+}
+
+// Statistics and status of a solve from its host copies.
+zi_status solve_end_finish(SolveCtx &c, zi_solve_stats *st, const EndCopy &h) {
+    const int n = c.sys->n, L = c.L, ldp = c.ldp;
+    const int32_t *h_iters = h.iters;
+    const double *h_rr = h.rr, *h_bb = h.bb, *h_true = h.tr;
+    const int32_t h_flag = *h.flag;
     if (st) {
         for (int k = 0; k < L; ++k) {
             if (st->iters) st->iters[k] = h_iters[k];
@@ -2646,9 +2680,16 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
                               double *const *T, zi_solve_stats *st, hipStream_t s) {
     // (gate, breakdown flag) of every head after a replay, and two pinned
     // host copies: the host reads one replay's copy while the next runs.
+    // After them in the same pinned block: every head's final statistics.
+    size_t end_bytes = 0;
+    for (int k = 0; k < nsys; ++k) {
+        const int L = o->columns ? o->n_columns : systems[k]->L;
+        end_bytes += EndCopy::bytes(L + (L & 1));
+    }
+    const size_t flag_bytes = ((sizeof(int32_t) * 4 * nsys + 7) / 8) * 8;
     int32_t *gates_d = nullptr, *gates_h = nullptr;
     ZI_HIP(hipMalloc(reinterpret_cast<void **>(&gates_d), sizeof(int32_t) * 2 * nsys));
-    if (hipHostMalloc(reinterpret_cast<void **>(&gates_h), sizeof(int32_t) * 4 * nsys) !=
+    if (hipHostMalloc(reinterpret_cast<void **>(&gates_h), flag_bytes + end_bytes) !=
         hipSuccess) {
         (void)hipFree(gates_d);
         set_error("hipHostMalloc of the batch flags failed");
@@ -2805,10 +2846,13 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
                 if (std::find(q.begin(), q.end(), k) != q.end()) {
                     // the queued replay found the head's gate closed and did
                     // nothing for it: its iteration count (which fixes the
-                    // ring slots and the reliable-update phase) goes back
+                    // ring slots and the reliable-update phase) goes back, and
+                    // its group is captured again without it (a recapture of
+                    // a few milliseconds costs less than the gated launches
+                    // of a head that stays in its group's graph)
                     cs[k].it -= chunk;
                     cs[k].flushed = cs[k].it;
-                    last[k / BATCH_GROUP].clear();   // its group is captured again
+                    last[k / BATCH_GROUP].clear();
                 }
             }
             const int ref = cs[k].refinements;
@@ -2823,15 +2867,33 @@ zi_status zi_solve_batch_impl(zi_system *const *systems, int32_t nsys, const zi_
             if (!m.empty()) r = launch(m, par);
         }
     }
-    (void)hipStreamSynchronize(s);   // no replay left running before graphs are destroyed
+    // Every head's final flush, T and statistics are queued behind the last
+    // replay; the graphs are destroyed (milliseconds of host work each) once
+    // the replays have run, while the GPU works on the heads' ends.
+    hipEvent_t replays_done = events[ngroups + 1];
+    const bool ev_ok = hipEventRecord(replays_done, s) == hipSuccess;
+    std::vector<EndCopy> ends(nsys);
+    char *endbuf = reinterpret_cast<char *>(gates_h) + flag_bytes;
+    for (size_t k = 0, off = 0; r == ZI_OK && k < (size_t)nsys; ++k) {
+        ends[k].carve(endbuf + off, cs[k].ldp);
+        off += EndCopy::bytes(cs[k].ldp);
+        r = solve_end_enqueue(cs[k], T[k], st ? &st[k] : nullptr, s, ends[k]);
+    }
+    if (!ev_ok || hipEventSynchronize(replays_done) != hipSuccess)
+        (void)hipStreamSynchronize(s);   // no replay left running before graphs are destroyed
     for (auto &g : gsets) g.clear();
     for (auto e : grave) (void)hipGraphExecDestroy(e);
-    ZI_TRY(r);
-    zi_status worst = ZI_OK;
-    for (int k = 0; k < nsys; ++k) {
-        const zi_status e = solve_end(cs[k], T[k], st ? &st[k] : nullptr, s);
-        if (e != ZI_OK && worst == ZI_OK) worst = e;
+    const bool synced = hipStreamSynchronize(s) == hipSuccess;
+    zi_status worst = r;
+    if (r == ZI_OK && !synced) {
+        set_error("hipStreamSynchronize failed");
+        worst = ZI_EDEVICE;
     }
+    if (worst == ZI_OK)
+        for (int k = 0; k < nsys; ++k) {
+            const zi_status e = solve_end_finish(cs[k], st ? &st[k] : nullptr, ends[k]);
+            if (e != ZI_OK && worst == ZI_OK) worst = e;
+        }
     return worst;
 }
 

@@ -42,3 +42,22 @@ def test_calibration_and_traffic_file(tmp_path):
 def test_source_hash_is_stable():
     assert counters.source_hash() == counters.source_hash()
     assert len(counters.source_hash()) == 16
+
+
+def test_phase_gaps(tmp_path):
+    # two phases cut at a marker; overlapping kernels count once as busy
+    path = tmp_path / "trace.csv"
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writerow(["k_a", 0, 10_000])
+        w.writerow(["k_b", 5_000, 20_000])        # overlaps k_a
+        w.writerow(["k_c", 80_000, 90_000])       # after a 60 us gap
+        w.writerow(["zi::k_copy2(x)", 100_000, 101_000])
+        w.writerow(["k_d", 200_000, 210_000])
+    ph = counters.phase_gaps(str(path))
+    assert len(ph) == 2
+    assert ph[0]["span_us"] == 90.0 and ph[0]["busy_us"] == 30.0 and ph[0]["idle_us"] == 60.0
+    assert ph[0]["dispatches"] == 3 and ph[0]["gaps_over_50us"] == 1
+    assert ph[0]["longest_gaps_us"] == [60.0]
+    assert ph[1]["busy_us"] == 10.0 and ph[1]["idle_us"] == 0.0
