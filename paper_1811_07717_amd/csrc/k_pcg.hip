@@ -1,25 +1,34 @@
 // Transfer matrix T = A^-1 B (App. A.4) by the diagonally preconditioned
 // conjugate gradient of Sec. 2.3.1, run on all electrode columns at once.
 //
-// Every column runs its own textbook PCG (its own alpha, beta, rho and stop
-// test); the columns only share the sweeps over A.  Block vectors are n x ldp
-// row-major (node-major), ldp = L rounded up to even; padding columns are
-// zero and inactive.
+// Every column runs its own PCG (its own alpha, beta, rho and stop test);
+// the columns only share the sweeps over A.  Block vectors are n x ldp
+// row-major (node-major) in the solver's row order, ldp = L rounded up to
+// even; padding columns are zero and inactive.
 //
-// Kernels per iteration:
-//   spmm_pq   Q = A P            + per-column partial p.q
-//   red_alpha alpha = rho / p.q  (one block per column, fixed order)
-//   update    X += alpha P, R -= alpha Q + partials r.D^-1 r and r.r
-//   red_beta  stop test, beta = rho'/rho, iteration counts
-//   pupdate   P = D^-1 R + beta P
+// Two forms of the iteration.  Single-reduction (Chronopoulos-Gear, the FP64
+// default), per iteration:
+//   spmm_sr      S = A D^-1 R_k + beta S   + partials of delta = z.Az
+//   red_alpha_sr alpha from gamma, delta and the previous alpha and beta
+//   update       R_{k+1} = R_k - alpha S  + partials of r.D^-1 r, r.r
+//   red_beta     stop test, beta
+//   pflush       every 16 iterations: the lazy search directions and X
+// Classic (and the mixed-precision mode, with float32 P, Q and R):
+//   spmm_pq      Q = A P                  + partials of p.q
+//   red_alpha, update (R -= alpha Q), red_beta, pupdate (P = D^-1 R + beta P),
+//   and every 16 iterations xflush (X += the last 16 alpha P).
 //
 // Tiling: a wave holds 64/LPR rows; each lane owns NV column pairs (double2).
-// A block (4 waves) owns a (row tile, column chunk of CW = 2 LPR NV columns).
-// Blocks are numbered so that the 8 XCDs (block b runs on XCD b mod 8) each
-// receive a contiguous range of tiles: consecutive rows (and their shared
-// neighbours) stay in one XCD's L2.  Dot-product partials are reduced inside
-// the block in a fixed order and across blocks by the red_* kernels in a
-// fixed order, so results are bitwise reproducible.
+// A block (4 waves) owns rows of one column chunk of CW = 2 LPR NV columns.
+// Blocks are numbered so that each of the 8 XCDs (block b runs on XCD b
+// mod 8) receives contiguous rows: rows that share neighbours stay in one
+// XCD's L2.  Schedules: chunk (a block per row range), cooperative front
+// (the blocks of an XCD sweep its rows together, in slabs), and the LDS ring
+// (a block per row range and 16-column chunk, the gathered rows in LDS).
+// Reproducibility: every entry of a product is formed in CSR order whatever
+// the tile; the SpMM's dot products are summed on fixed grids (exact in any
+// grouping), the other kernels' in a fixed order with one fixed geometry, so
+// T is bitwise the same for every tile and every run.
 #include <algorithm>
 #include <chrono>
 #include <climits>
