@@ -915,9 +915,9 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_ring(Geom g, const int32_t *__re
 }
 
 // Rows per lane per step in the streaming kernels (measured best on gfx950:
-// the residual update of FP64 vectors gains from more loads in flight).
+// the residual update gains from more loads in flight).
 template <class TP>
-constexpr int unroll_update() { return sizeof(TP) == 8 ? 8 : 4; }   // k_update
+constexpr int unroll_update() { return 8; }                           // k_update
 constexpr int UNROLL_P = 4;                                           // k_pupdate
 
 // Load form of the streaming kernels.  FP32 vectors are loaded without a
@@ -1731,11 +1731,20 @@ void occupancy_of(GK k, int *out) {
 // fastest for it on the 2 mm sphere, whatever tile the SpMM uses.
 constexpr int FLUSH_TILE = 13;   // lpr32_nv2_cw128_front
 // Residual update, direction update, residual b - A x and the lazy-P flush
-// run with one geometry for a given column count, whatever the SpMM tile:
-// 128-column front chunks of 32 lanes x 2 pairs from 128 columns up, else
-// the narrowest front tile that holds every column (no idle lanes on
-// 32-96 column blocks).
-int stream_tile(int ldp) { return ldp >= 128 ? FLUSH_TILE : auto_tile(ldp); }
+// run with one geometry for a given column count and precision, whatever
+// the SpMM tile: 128-column front chunks of 32 lanes x 2 pairs from 128
+// columns up, else the narrowest front tile that holds every column (no idle
+// lanes on 32-96 column blocks).  Float32 blocks of more than 128 columns
+// take 256-column chunks, a row of up to 1 KB per lane group (the float32
+// residual update at 1 mm, 256 columns: 1.97 against 2.05 ms).
+constexpr int STREAM_TILE_F32 = 11;   // lpr64_nv2_cw256_front
+int stream_tile(int ldp, bool f32 = false) {
+    if (f32 && ldp > 128) return STREAM_TILE_F32;
+    return ldp >= 128 ? FLUSH_TILE : auto_tile(ldp);
+}
+static_assert(kTiles[STREAM_TILE_F32].lpr == 64 && kTiles[STREAM_TILE_F32].nv == 2 &&
+                  kTiles[STREAM_TILE_F32].front == 1,
+              "float32 streaming geometry");
 static_assert(kTiles[FLUSH_TILE].lpr == 32 && kTiles[FLUSH_TILE].nv == 2 &&
                   kTiles[FLUSH_TILE].front == 1,
               "flush geometry");
@@ -2305,7 +2314,7 @@ zi_status solve_begin(zi_system *sys, const zi_solve_opts *o, SolveCtx &c, hipSt
     c.ws = ws;
     c.g = make_geom_for(c.sr ? GK::SPMM_SR : c.mixed ? GK::SPMM_DOT32 : GK::SPMM_DOT64, n, ldp,
                         tile);
-    c.stile = stream_tile(ldp);
+    c.stile = stream_tile(ldp, c.mixed);
     c.rtile = kTiles[tile].ring ? c.stile : tile;
     c.grt = kTiles[tile].ring ? make_geom_for(GK::SPMM64, n, ldp, c.rtile) : c.g;
     c.gu = make_geom_for(c.mixed ? GK::UPDATE32 : GK::UPDATE64, n, ldp, c.stile);
