@@ -30,7 +30,8 @@ KERNEL_SOURCES = ["paper_1811_07717_amd/csrc/k_pcg.hip",
 
 # rocprofv3 kernel name -> solver kernel key used by bench.py
 KERNELS = [(re.compile(r"k_spmm<.*, true>"), "spmm_pq"),
-           (re.compile(r"k_spmm_sr(<|_ring)"), "spmm_sr"),
+           (re.compile(r"k_spmm_sr<|k_spmm_ring<double, true>"), "spmm_sr"),
+           (re.compile(r"k_spmm_ring<.*, false>"), "spmm_pq"),
            (re.compile(r"k_update<"), "update"),
            (re.compile(r"k_pupdate<"), "pupdate"),
            (re.compile(r"k_xflush<"), "xflush"),
@@ -58,7 +59,7 @@ def per_kernel(path, spmm_args=None):
             for pat, key in KERNELS:
                 if pat.search(name):
                     if (spmm_args and key.startswith("spmm")
-                            and (f"<{spmm_args}" if spmm_args != "ring" else "_ring(")
+                            and (f"<{spmm_args}" if spmm_args != "ring" else "k_spmm_ring<")
                             not in name):
                         break
                     vals[key].append(float(r["Counter_Value"]))

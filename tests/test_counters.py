@@ -61,3 +61,18 @@ def test_phase_gaps(tmp_path):
     assert ph[0]["dispatches"] == 3 and ph[0]["gaps_over_50us"] == 1
     assert ph[0]["longest_gaps_us"] == [60.0]
     assert ph[1]["busy_us"] == 10.0 and ph[1]["idle_us"] == 0.0
+
+
+def test_ring_kernels_are_classified(tmp_path):
+    ring = "void (anonymous namespace)::k_spmm_ring<double, true>(Geom, int const*)"
+    ringf = "void (anonymous namespace)::k_spmm_ring<float, false>(Geom, int const*)"
+    front = "void (anonymous namespace)::k_spmm_sr<8, 1>(Geom, int const*)"
+    upd = "void (anonymous namespace)::k_update<32, 2, double>(Geom, ...)"
+    copy = "zi::(anonymous namespace)::k_copy2(double2 const*, double2*, unsigned long)"
+    rows = [(copy, 512.0), (ring, 100.0), (ringf, 40.0), (front, 7.0), (upd, 50.0)]
+    _write(tmp_path / "f.csv", rows)
+    _write(tmp_path / "w.csv", rows)
+    res = counters.per_kernel(tmp_path / "f.csv", "ring")
+    assert res["spmm_sr"] == (100.0, 1) and res["spmm_pq"] == (40.0, 1)
+    res = counters.per_kernel(tmp_path / "f.csv", "8, 1")
+    assert res["spmm_sr"] == (7.0, 1) and "spmm_pq" not in res
