@@ -396,21 +396,25 @@ void k_spmm(Geom g, const int32_t *__restrict__ rp,
         XT xs[NV];
         bool self;
         row_product<LPR, NV, TV, TX>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc, xs, self);
+        // Dot terms (and the load of a row without a diagonal entry) before
+        // the stores: one counter tracks a wave's loads and stores in flight,
+        // so waiting for a load issued after a store waits for the store too.
+        if (WITH_DOT) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            if (!ln.ok[v]) continue;
-            TX *y = Y + (size_t)row * g.ldp + ln.c[v];
-            stpair_nt(y, acc[v]);
-            if (WITH_DOT) {
+            for (int v = 0; v < NV; ++v) {
+                if (!ln.ok[v]) continue;
                 XT xr = xs[v];
                 if (!self) ldpair(X + (size_t)row * g.ldp + ln.c[v], xr);
                 const double2 p = wide(xr);
-                const double2 q = as_stored(acc[v], (const TX *)y);
+                const double2 q = as_stored(acc[v], (const TX *)Y);
                 const int cl = 2 * (ln.lr + LPR * v);
                 fold_add(p.x, q.x, m1[cl], f2, dotacc[0][v].x, dotacc[1][v].x);
                 fold_add(p.y, q.y, m1[cl + 1], f2, dotacc[0][v].y, dotacc[1][v].y);
             }
         }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (ln.ok[v]) stpair_nt(Y + (size_t)row * g.ldp + ln.c[v], acc[v]);
     });
     if (WITH_DOT) {
         double *const parts[2] = {part, part + (size_t)g.nrt * g.ldp};
@@ -462,19 +466,25 @@ void k_spmm_sr(Geom g, const int32_t *__restrict__ rp,
         bool self;
         row_product<LPR, NV, double, double>(rp, ci, vs, R, g.ldp, row, ln.lr, ln.c, ln.ok, acc,
                                              xs, self);
+        // Dot terms (and the load of a row without a diagonal entry) before
+        // the stores: one counter tracks a wave's loads and stores in flight,
+        // so waiting for a load issued after a store waits for the store too.
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (!ln.ok[v]) continue;
-            const size_t o = (size_t)row * g.ldp + ln.c[v];
-            double2 sn;
-            sn.x = fma(be[v].x, so[v].x, acc[v].x);
-            sn.y = fma(be[v].y, so[v].y, acc[v].y);
-            stn2(S + o, sn);
             double2 xr = xs[v];
-            if (!self) xr = ld2(R + o);
+            if (!self) xr = ld2(R + (size_t)row * g.ldp + ln.c[v]);
             const int cl = 2 * (ln.lr + LPR * v);
             fold_add(xr.x * di, acc[v].x, m1[cl], f2, dotacc[0][v].x, dotacc[1][v].x);
             fold_add(xr.y * di, acc[v].y, m1[cl + 1], f2, dotacc[0][v].y, dotacc[1][v].y);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (!ln.ok[v]) continue;
+            double2 sn;
+            sn.x = fma(be[v].x, so[v].x, acc[v].x);
+            sn.y = fma(be[v].y, so[v].y, acc[v].y);
+            stn2(S + (size_t)row * g.ldp + ln.c[v], sn);
         }
     });
     double *const parts[2] = {part, part + (size_t)g.nrt * g.ldp};
