@@ -235,28 +235,42 @@ __device__ __forceinline__ double bcast(double v, int u) {
 // (lane u of the group holds entry u) and broadcast, so all gathers of X for
 // the batch are in flight together.  xs receives X[row, c..c+1] (the gather
 // of the diagonal entry; self tells whether the row has one), which spares
-// the dot product a second load of the row.
-template <int LPR, int NV, class TV, class TX>
+// the dot product a second load of the row.  after_index() issues the
+// caller's own loads for the row once the first batch's pairs are requested:
+// a wave waits for its loads in issue order, so loads issued before the
+// pairs would delay the gathers that depend on them.
+template <int LPR, int NV, class TV, class TX, class F>
 __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
                                             const int32_t *__restrict__ ci,
                                             const TV *__restrict__ va,
                                             const TX *__restrict__ X, int ldp, int row,
                                             int lr, const int c[NV], const bool ok[NV],
                                             typename Acc<TV>::type acc[NV],
-                                            typename Acc<TX>::type xs[NV], bool &self) {
+                                            typename Acc<TX>::type xs[NV], bool &self,
+                                            F &&after_index) {
     using XT = typename Acc<TX>::type;   // gathered pairs stay in storage precision
     constexpr int BATCH = LPR < 8 ? LPR : 8;
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = Acc<TV>::zero();
     self = false;
     const int s = rp[row], e = rp[row + 1];
+    // the first batch's (column, value) pairs, then the caller's loads
+    int jv = row;
+    TV av = TV(0);
+    if (lr < BATCH && lr < e - s) {
+        jv = __builtin_nontemporal_load(ci + s + lr);
+        av = __builtin_nontemporal_load(va + s + lr);
+    }
+    after_index();
     for (int kb = s; kb < e; kb += BATCH) {
         const int cnt = e - kb;
-        int jv = row;
-        TV av = TV(0);
-        if (lr < BATCH && lr < cnt) {
-            jv = __builtin_nontemporal_load(ci + kb + lr);
-            av = __builtin_nontemporal_load(va + kb + lr);
+        if (kb != s) {
+            jv = row;
+            av = TV(0);
+            if (lr < BATCH && lr < cnt) {
+                jv = __builtin_nontemporal_load(ci + kb + lr);
+                av = __builtin_nontemporal_load(va + kb + lr);
+            }
         }
         XT x[BATCH][NV];
         int jj[BATCH];
@@ -395,7 +409,8 @@ void k_spmm(Geom g, const int32_t *__restrict__ rp,
         AT acc[NV];
         XT xs[NV];
         bool self;
-        row_product<LPR, NV, TV, TX>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc, xs, self);
+        row_product<LPR, NV, TV, TX>(rp, ci, va, X, g.ldp, row, ln.lr, ln.c, ln.ok, acc, xs, self,
+                                     [] {});
         // Dot terms (and the load of a row without a diagonal entry) before
         // the stores: one counter tracks a wave's loads and stores in flight,
         // so waiting for a load issued after a store waits for the store too.
@@ -455,17 +470,20 @@ void k_spmm_sr(Geom g, const int32_t *__restrict__ rp,
     }
     __syncthreads();
     for_rows<LPR, NV>(sc, ln, [&](int row) {
-        // the row's S entries are requested before the gathers
+        // the row's S entries and D^-1 are requested after its column
+        // indices and before its gathers
         double2 so[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-            so[v] = (ln.ok[v] && beta) ? ldn2(S + (size_t)row * g.ldp + ln.c[v])
-                                       : make_double2(0.0, 0.0);
-        const double di = dinv[row];
+        double di;
         double2 acc[NV], xs[NV];
         bool self;
-        row_product<LPR, NV, double, double>(rp, ci, vs, R, g.ldp, row, ln.lr, ln.c, ln.ok, acc,
-                                             xs, self);
+        row_product<LPR, NV, double, double>(
+            rp, ci, vs, R, g.ldp, row, ln.lr, ln.c, ln.ok, acc, xs, self, [&] {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    so[v] = (ln.ok[v] && beta) ? ldn2(S + (size_t)row * g.ldp + ln.c[v])
+                                               : make_double2(0.0, 0.0);
+                di = dinv[row];
+            });
         // Dot terms (and the load of a row without a diagonal entry) before
         // the stores: one counter tracks a wave's loads and stores in flight,
         // so waiting for a load issued after a store waits for the store too.
