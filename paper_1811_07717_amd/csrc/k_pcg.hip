@@ -18,7 +18,9 @@
 //   red_alpha, update (R -= alpha Q), red_beta, pupdate (P = D^-1 R + beta P),
 //   and every 16 iterations xflush (X += the last 16 alpha P).
 //
-// Tiling: a wave holds 64/LPR rows; each lane owns NV column pairs (double2).
+// Tiling: a wave holds 64/LPR rows; each lane owns NV column pairs (double2;
+// the float32 products with two pairs per lane take four adjacent columns
+// per lane when the width allows one 16-byte load per gathered row).
 // A block (4 waves) owns rows of one column chunk of CW = 2 LPR NV columns.
 // Blocks are numbered so that each of the 8 XCDs (block b runs on XCD b
 // mod 8) receives contiguous rows: rows that share neighbours stay in one
@@ -318,7 +320,7 @@ __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
 template <int LPR, int NV, int NQ>
 __device__ __forceinline__ void block_partials(const Geom &g, const Lane<LPR, NV> &ln, int cc,
                                                int prow, const double2 (&acc)[NQ][NV],
-                                               double *const (&part)[NQ]) {
+                                               double *const (&part)[NQ], bool quad = false) {
     constexpr int RS = Lane<LPR, NV>::RSTEP;
     constexpr int CW = Lane<LPR, NV>::CW;
     __shared__ double red[NQ][RS][CW];
@@ -326,7 +328,7 @@ __device__ __forceinline__ void block_partials(const Geom &g, const Lane<LPR, NV
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const int cl = 2 * (ln.lr + LPR * v);
+            const int cl = quad ? 4 * ln.lr + 2 * v : 2 * (ln.lr + LPR * v);
             red[q][ln.slot][cl] = acc[q][v].x;
             red[q][ln.slot][cl + 1] = acc[q][v].y;
         }
@@ -380,6 +382,81 @@ __device__ __forceinline__ void for_rows(const Sched &sc, const Lane<LPR, NV> &l
     }
 }
 
+// Rows of a float32 SpMM with two column pairs per lane, when the padded
+// width is a multiple of 4: lane lr owns the four adjacent columns
+// c0 = cc CW + 4 lr .. c0 + 3 and gathers them with one 16-byte load (the
+// pair layout needs two 8-byte loads per row).  Products, their order and
+// the dot terms are those of row_product; the partials use the quad map.
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+template <int LPR, class TV, bool WITH_DOT>
+__device__ __forceinline__ void spmm_rows_quad(const Geom &g, const Sched &sc,
+                                               const Lane<LPR, 2> &ln,
+                                               const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ ci,
+                                               const TV *__restrict__ va,
+                                               const float *__restrict__ X,
+                                               float *__restrict__ Y, const double *m1,
+                                               double f2, double2 (&dotacc)[2][2]) {
+    using AT = typename Acc<TV>::type;
+    constexpr int BATCH = LPR < 8 ? LPR : 8;
+    constexpr int CW = Lane<LPR, 2>::CW;
+    const int lr = ln.lr;
+    const int c0 = sc.cc * CW + 4 * lr;
+    const bool ok = c0 < g.ldp;
+    for_rows<LPR, 2>(sc, ln, [&](int row) {
+        AT acc[2] = {Acc<TV>::zero(), Acc<TV>::zero()};
+        fvec4 xs = {0.f, 0.f, 0.f, 0.f};
+        bool self = false;
+        const int s = rp[row], e = rp[row + 1];
+        for (int kb = s; kb < e; kb += BATCH) {
+            const int cnt = e - kb;
+            int jv = row;
+            TV av = TV(0);
+            if (lr < BATCH && lr < cnt) {
+                jv = __builtin_nontemporal_load(ci + kb + lr);
+                av = __builtin_nontemporal_load(va + kb + lr);
+            }
+            fvec4 x[BATCH];
+            int jj[BATCH];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                jj[u] = bcast<LPR>(jv, u);
+                if (u < cnt && ok)
+                    x[u] = *reinterpret_cast<const fvec4 *>(X + (size_t)jj[u] * g.ldp + c0);
+                else
+                    x[u] = fvec4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const TV a = bcast<LPR>(av, u);
+                if (u < cnt) {
+                    acc[0].x = fma(a, (TV)x[u].x, acc[0].x);
+                    acc[0].y = fma(a, (TV)x[u].y, acc[0].y);
+                    acc[1].x = fma(a, (TV)x[u].z, acc[1].x);
+                    acc[1].y = fma(a, (TV)x[u].w, acc[1].y);
+                    if (jj[u] == row) {
+                        self = true;
+                        xs = x[u];
+                    }
+                }
+            }
+        }
+        if (!ok) return;
+        float *y = Y + (size_t)row * g.ldp + c0;
+        const fvec4 q4 = {(float)acc[0].x, (float)acc[0].y, (float)acc[1].x, (float)acc[1].y};
+        if (WITH_DOT) {
+            fvec4 xr = xs;
+            if (!self) xr = *reinterpret_cast<const fvec4 *>(X + (size_t)row * g.ldp + c0);
+            const int cl = 4 * lr;
+            fold_add((double)xr.x, (double)q4.x, m1[cl], f2, dotacc[0][0].x, dotacc[1][0].x);
+            fold_add((double)xr.y, (double)q4.y, m1[cl + 1], f2, dotacc[0][0].y, dotacc[1][0].y);
+            fold_add((double)xr.z, (double)q4.z, m1[cl + 2], f2, dotacc[0][1].x, dotacc[1][1].x);
+            fold_add((double)xr.w, (double)q4.w, m1[cl + 3], f2, dotacc[0][1].y, dotacc[1][1].y);
+        }
+        __builtin_nontemporal_store(q4, reinterpret_cast<fvec4 *>(y));
+    });
+}
+
 // ---------------------------------------------------------------------------
 
 // Y = A X; with WITH_DOT also the partials of sum_i X[i,c] Y[i,c] (in FP64,
@@ -414,7 +491,15 @@ void k_spmm(Geom g, const int32_t *__restrict__ rp,
         }
         __syncthreads();
     }
-    for_rows<LPR, NV>(sc, ln, [&](int row) {
+    bool quad = false;
+    if constexpr (std::is_same<TX, float>::value && NV == 2) {
+        if ((g.ldp & 3) == 0 &&
+            ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15) == 0) {
+            quad = true;
+            spmm_rows_quad<LPR, TV, WITH_DOT>(g, sc, ln, rp, ci, va, X, Y, m1, f2, dotacc);
+        }
+    }
+    if (!quad) for_rows<LPR, NV>(sc, ln, [&](int row) {
         AT acc[NV];
         XT xs[NV];
         bool self;
@@ -442,7 +527,7 @@ void k_spmm(Geom g, const int32_t *__restrict__ rp,
     });
     if (WITH_DOT) {
         double *const parts[2] = {part, part + (size_t)g.nrt * g.ldp};
-        block_partials<LPR, NV, 2>(g, ln, sc.cc, sc.prow, dotacc, parts);
+        block_partials<LPR, NV, 2>(g, ln, sc.cc, sc.prow, dotacc, parts, quad);
     }
 }
 
