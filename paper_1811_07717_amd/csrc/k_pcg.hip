@@ -261,6 +261,51 @@ __device__ __forceinline__ void row_product(const int32_t *__restrict__ rp,
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = Acc<TV>::zero();
     self = false;
+    if constexpr (LPR == 64) {
+        // one row per wave: the row's pointers and (column, value) pairs are
+        // wave-uniform and come through scalar loads, whose waits are apart
+        // from those of the vector loads and stores
+        const int rw = __builtin_amdgcn_readfirstlane(row);
+        const int s = rp[rw], e = rp[rw + 1];
+        after_index();
+        for (int kb = s; kb < e; kb += 8) {
+            const int cnt = e - kb;
+            int jj[8];
+            TV a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = min(kb + u, e - 1);
+                jj[u] = ci[k];
+                a[u] = va[k];
+            }
+            XT x[8][NV];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    if (u < cnt && ok[v])
+                        ldpair(X + (size_t)jj[u] * ldp + c[v], x[u][v]);
+                    else
+                        x[u][v] = Acc<TX>::zero();
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (u < cnt) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        acc[v].x = fma(a[u], (TV)x[u][v].x, acc[v].x);
+                        acc[v].y = fma(a[u], (TV)x[u][v].y, acc[v].y);
+                    }
+                    if (jj[u] == rw) {
+                        self = true;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) xs[v] = x[u][v];
+                    }
+                }
+            }
+        }
+        return;
+    }
     constexpr bool PEEL = !std::is_same<std::decay_t<F>, NoLoads>::value;
     const int s = rp[row], e = rp[row + 1];
     // the first batch's (column, value) pairs, then the caller's loads
